@@ -1,0 +1,123 @@
+/*
+ * oracle.h -- plain, slow, single-threaded C reference for the annealing hot
+ * path of "Linear-time classical approximate optimization of cubic-lattice
+ * classical spin glasses" (Gangat, arXiv 2501.17267).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this code; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no source with the HIP
+ * path: every definition below is written out again, from the paper and the
+ * published definitions of Philox4x32-10 and splitmix64, in the most direct
+ * form.
+ *
+ * What is computed, and where the paper fixes it:
+ *   energy      Eq. (1), H = sum over nearest-neighbour pairs J_ij s_i s_j
+ *   epsilon     Eq. (2), eps = (E - E_gs)/|E_gs|
+ *   sa_run      App. D (Simulated Annealing): Metropolis sweeps over a
+ *               beta schedule, one read = the final configuration
+ *   pt_run      App. D (Parallel Tempering): Metropolis sweeps of T walkers
+ *               on a ladder of betas plus neighbour replica exchange
+ *   make_inst   Sec. II: tile-planted instance with a gauge-scrambled
+ *               planted ground state and exactly known E_gs (synthetic
+ *               stand-in: the tile classes of the paper are defined only
+ *               in its references)
+ *   Boltzmann   App. A: the target law p(s) ~ exp(-beta H(s)) that fixes
+ *               the Metropolis acceptance min(1, exp(-beta dE))
+ *
+ * Parity pins for every function live in tests/test_oracle_*.py; no function
+ * here is "parity unpinned".
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- lattice -------------------------------------------------------------
+ * Box Lx x Ly x Lz, site i = x + Lx*(y + Ly*z).  Directions d = 0..5 are
+ * +x, -x, +y, -y, +z, -z.  Neighbours wrap periodically; an open box is a
+ * periodic one whose wrap-around couplings are zero.
+ * J is int8 [6][N]: J[d*N + i] couples site i to its d-neighbour, so each
+ * bond appears twice (J[+x][i] == J[-x][i+x] and so on). */
+int64_t orc_site(int Lx, int Ly, int Lz, int x, int y, int z);
+int64_t orc_nbr(int Lx, int Ly, int Lz, int64_t i, int d);
+
+/* ---- splitmix64 (Steele, Lea, Flood 2014) -------------------------------- */
+uint64_t orc_sm64_next(uint64_t *state);
+
+/* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) -------------------
+ * out[0..3] = Philox4x32_10(counter ctr[0..3], key (k0, k1)). */
+void orc_philox(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]);
+
+/* ---- instance generator (synthetic tile planting) ------------------------
+ * cls = number of frustrated faces every tile must have (0, 2, 4 or 6);
+ * -1 = no face filter.  periodic = 1 for a periodic box (all dims even),
+ * 0 for an open box.  Writes J[6][N], planted[N] (+1/-1) and E_gs. */
+int orc_make_instance(int Lx, int Ly, int Lz, int periodic, int cls, uint64_t seed,
+                      int8_t *J, int8_t *planted, int64_t *E_gs);
+
+/* ---- energy and optimality gap ------------------------------------------ */
+int64_t orc_energy(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *s);
+int64_t orc_local_field(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *s, int64_t i);
+double  orc_epsilon(int64_t E, int64_t E_gs);
+
+/* ---- schedules and threshold tables ---------------------------------------
+ * kind 0: linear  beta_s = b0 + (b1-b0) s/(S-1)
+ * kind 1: geometric beta_s = b0 (b1/b0)^(s/(S-1));  S == 1 gives b0. */
+int orc_schedule(int kind, double b0, double b1, int S, double *beta);
+/* thr[r*K + (k-1)] = min(2^32-1, floor(exp(-2 beta_r k) 2^32)), k = 1..K.
+ * A proposal with dE = 2k > 0 is accepted iff u < thr (u a Philox word). */
+int orc_thresholds(const double *beta, int S, int K, uint32_t *thr);
+/* Replica-exchange table for ladder pair (k, k+1):
+ * thrx[k*M + (m-1)] = min(2^32-1, floor(exp(-(beta_{k+1}-beta_k) 2m) 2^32)). */
+int orc_exchange_thresholds(const double *beta, int T, int M, uint32_t *thrx);
+
+/* ---- simulated annealing ---------------------------------------------------
+ * Cubic periodic lattice, L even >= 4.  Replica r (r = 0..n_rep-1) carries
+ * the Philox counter word rep0 + r; chain is the fourth counter word.
+ * init_random = 1 draws the initial spins from the init stream, 0 starts
+ * from spins[] as given.  Sweeps sweep0 .. sweep0+S-1 use thr rows 0..S-1.
+ * energy[r] = final energy; emin[r] (nullable) = lowest energy seen at the
+ * end of a sweep.  check = 1 recomputes the energy after every sweep and
+ * returns -2 if the tracked value differs.  Returns 0 on success. */
+int orc_sa_run(int L, const int8_t *J, uint64_t seed, uint32_t chain, uint32_t rep0, int n_rep,
+               const uint32_t *thr, int K, int S, int sweep0, int init_random,
+               int8_t *spins, int64_t *energy, int64_t *emin, int check);
+
+/* Same chain, with the sites of each colour visited in reverse order.  Used
+ * only to show that the order inside a colour does not change the result. */
+int orc_sa_run_reversed(int L, const int8_t *J, uint64_t seed, uint32_t chain, uint32_t rep0,
+                        int n_rep, const uint32_t *thr, int K, int S, int sweep0,
+                        int init_random, int8_t *spins, int64_t *energy);
+
+/* ---- parallel tempering -----------------------------------------------------
+ * One run = T walkers (memory slots w = 0..T-1).  pos[w] = ladder slot of
+ * walker w.  Step t (t = step0 .. step0+n_steps-1): every walker makes one
+ * sweep with thresholds row pos[w] and Metropolis counter (., 2t+c, w, run);
+ * then ladder pairs (k, k+1) with k = t mod 2, t mod 2 + 2, ... exchange
+ * walkers with probability min(1, exp(-(beta_{k+1}-beta_k) D)),
+ * D = E(walker at k) - E(walker at k+1), drawn from Philox word 0 of
+ * counter (k, t, 0xFFFFFFFF, run).
+ * spins [T][N], energy [T], pos [T] in/out (init_random = 1 resets spins
+ * from the init stream and pos to identity); emin_trace [n_steps] nullable;
+ * swap_acc [T-1] nullable, accumulated. */
+int orc_pt_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
+               const uint32_t *thr, int K, const uint32_t *thrx, int M,
+               int n_steps, int step0, int init_random,
+               int8_t *spins, int64_t *energy, int32_t *pos,
+               int64_t *emin_trace, uint32_t *swap_acc, int check);
+
+/* ---- initial spins (init stream) ------------------------------------------ */
+void orc_init_spins(int L, uint64_t seed, uint32_t chain, uint32_t replica, int8_t *s);
+
+/* Philox word used by the Metropolis proposal at site i, sweep s, colour c. */
+uint32_t orc_metropolis_uniform(int L, uint64_t seed, uint32_t chain, uint32_t replica,
+                                int s, int64_t i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
