@@ -1,0 +1,195 @@
+/*
+ * sgmi.h -- C ABI of the MI355X (gfx950) annealing library for cubic-lattice
+ * Ising spin glasses.
+ *
+ * The library implements the data-parallel hot path behind the approximate
+ * optimisation of Gangat, "Linear-time classical approximate optimization of
+ * cubic-lattice classical spin glasses" (arXiv 2501.17267):
+ *   - minimise H(s) = sum over nearest-neighbour pairs J_ij s_i s_j over
+ *     s in {-1,+1}^N (Sec. I, Eq. 1) on a periodic L x L x L lattice;
+ *   - by fixed-sweep-count Metropolis simulated annealing and by parallel
+ *     tempering (App. D);
+ *   - scored by the optimality gap eps = (E - E_gs)/|E_gs| (Sec. I.A, Eq. 2)
+ *     against the exactly known planted ground-state energy of a
+ *     tile-planted instance (Sec. II).
+ *
+ * Conventions shared by every call
+ *   - Lattice: L even, 4 <= L <= SG_MAX_L, N = L^3, site i = x + L*(y + L*z),
+ *     periodic in all three directions.  Colour of a site = (x+y+z) mod 2.
+ *   - Couplings: int8 J[6][N] in device memory, direction order
+ *     +x, -x, +y, -y, +z, -z; J[d][i] couples site i to its d-neighbour, so
+ *     each bond is stored twice and the two copies must agree.  Values must
+ *     lie in [-4, 4] (sg_check_instance verifies both).
+ *   - Spins: int8 +1 / -1, natural site order, [n][N] per call.
+ *   - Energies: int32 exact, Eq. 1 with each pair counted once.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed & 0xFFFFFFFF, seed >> 32) and counters
+ *       Metropolis proposal at site (x,y,z), colour c, sweep s, replica r:
+ *         (col * ceil(L/4) + floor(z/4), 2s + c, r, chain), word z mod 4,
+ *         where col = floor(x/2) + (L/2) y;
+ *       initial spin of site i of replica r: (floor(i/4), 0xFFFFFFFF, r,
+ *         chain), word i mod 4, spin -1 iff the word's top bit is set;
+ *       PT exchange of ladder pair k at step t of run `chain`:
+ *         (k, t, 0xFFFFFFFF, chain), word 0.
+ *     Results depend only on these counters, never on the launch shape.
+ *   - Metropolis step (App. D, with the acceptance min(1, exp(-beta dE)) of
+ *     the Boltzmann law in App. A): dE = -2 s_i h_i = 2k; k <= 0 always
+ *     flips; k > 0 flips iff k <= K and u < thr[row][k-1].  Colour 0 sites
+ *     are all updated before colour 1 sites in every sweep.
+ *   - Device pointers are borrowed: the library keeps none of them after a
+ *     call returns and allocates no device memory in these calls.  `stream`
+ *     is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *     validate their arguments on the host, enqueue their kernels and return
+ *     without waiting for the device.
+ *   - Return value: SG_OK (0) or a negative status; sg_last_error() gives a
+ *     message for the calling thread.  No C++ exception crosses this ABI.
+ */
+#ifndef SGMI_H
+#define SGMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_OK 0
+#define SG_EINVAL (-1)       /* invalid argument (shape, range, null pointer) */
+#define SG_ENOMEM (-2)       /* host or device allocation failed */
+#define SG_EDEVICE (-3)      /* a HIP runtime call failed */
+#define SG_ERANGE (-4)       /* value outside what the tables cover */
+#define SG_EBUSY (-5)        /* resource full */
+#define SG_ENOTFOUND (-6)    /* unknown handle or request */
+#define SG_EUNSUPPORTED (-7) /* valid input this build cannot run */
+
+#define SG_MAX_L 64          /* largest lattice the kernels accept */
+#define SG_K_MAX 24          /* 6 neighbours x |J| <= 4 */
+
+/* An instance: the couplings of Eq. 1 plus its planted ground-state energy.
+ * jenc: optional device buffer of sg_jenc_bytes(L) bytes filled by
+ * sg_encode_instance; required for L > SG_LDS_MAX_L, used to speed up the
+ * set-up of smaller ones when present. */
+typedef struct sg_instance {
+    int32_t L;
+    int32_t reserved;
+    const int8_t *J;       /* device int8 [6][L^3] */
+    const uint32_t *jenc;  /* device, nullable */
+    int64_t E_gs;          /* planted ground-state energy, nonzero */
+    uint32_t chain;        /* fourth Philox counter word of this instance's chains */
+    uint32_t reserved2;
+} sg_instance;
+
+#define SG_LDS_MAX_L 24    /* couplings held in LDS up to this L */
+
+/* Simulated annealing of n_rep independent replicas (App. D: Metropolis
+ * sweeps over a beta schedule, one read = the final configuration).
+ * Replica r uses Philox counter word rep0 + r.  Sweeps sweep0 ..
+ * sweep0+n_sweeps-1 take thr rows 0 .. n_sweeps-1, so a run split into
+ * chunks equals the uninterrupted run. */
+typedef struct sg_sa_args {
+    int32_t n_rep;       /* >= 1 */
+    uint32_t rep0;       /* counter word of replica 0 */
+    int32_t n_sweeps;    /* >= 1 */
+    int32_t sweep0;      /* absolute index of the first sweep, >= 0 */
+    int32_t K;           /* row length of thr, 1..SG_K_MAX */
+    int32_t init_random; /* 1: draw initial spins from the init stream; 0: use spins[] */
+    uint64_t seed;       /* Philox key */
+} sg_sa_args;
+
+/* thr:    device uint32 [n_sweeps][K] (from sg_make_thresholds)
+ * spins:  device int8 [n_rep][N], input when init_random == 0, output always
+ * energy: device int32 [n_rep], final energies
+ * emin:   device int32 [n_rep] or NULL: lowest energy at the end of a sweep */
+int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
+              int8_t *spins, int32_t *energy, int32_t *emin, void *stream);
+
+/* Parallel tempering (App. D): n_runs independent runs of T walkers on an
+ * ascending beta ladder.  Step t: every walker w makes one sweep with the
+ * thresholds of its ladder slot pos[w] (Metropolis counter (., 2t+c, w,
+ * run)), then ladder pairs (k, k+1) with k = t mod 2, t mod 2 + 2, ...
+ * exchange their walkers with probability
+ * min(1, exp(-(beta_{k+1}-beta_k) D)), D = E(walker at k) - E(walker at k+1),
+ * i.e. D <= 0 always, else m = D/2 <= M and u < thrx[k][m-1].
+ * Run j uses chain = run0 + j as its counter word. */
+typedef struct sg_pt_args {
+    int32_t n_runs;      /* >= 1 */
+    uint32_t run0;
+    int32_t T;           /* walkers per run, 2..SG_PT_MAX_T */
+    int32_t n_steps;     /* >= 1 */
+    int32_t step0;       /* absolute index of the first step, >= 0 */
+    int32_t K;           /* row length of thr */
+    int32_t M;           /* row length of thrx, >= 1 */
+    int32_t init_random; /* 1: init-stream spins and pos[w] = w; 0: use spins[] and pos[] */
+    uint64_t seed;
+} sg_pt_args;
+
+#define SG_PT_MAX_T 64
+
+/* thr:        device uint32 [T][K], row k = ladder slot k
+ * thrx:       device uint32 [T-1][M] (from sg_make_exchange_thresholds)
+ * spins:      device int8 [n_runs][T][N] in/out (walker-major)
+ * energy:     device int32 [n_runs][T] out
+ * pos:        device int32 [n_runs][T] in/out, walker -> ladder slot
+ * emin_trace: device int32 [n_runs][n_steps] or NULL: min walker energy after each step
+ * swap_acc:   device uint32 [n_runs][T-1] or NULL: accepted exchanges per pair, added to */
+int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
+           const uint32_t *thrx, int8_t *spins, int32_t *energy, int32_t *pos,
+           int32_t *emin_trace, uint32_t *swap_acc, void *stream);
+
+/* Energy (Eq. 1) of n_rep configurations spins [n_rep][N] -> energy [n_rep]. */
+int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t *energy_out,
+           void *stream);
+
+/* Optimality gap (Eq. 2): eps[i] = (energy[i] - E_gs) / |E_gs| in double,
+ * from exact integers.  energy and eps_out are device arrays of n entries. */
+int epsilon(const int32_t *energy, int64_t n, int64_t E_gs, double *eps_out, void *stream);
+
+/* ---- host helpers (synchronous, no device work) ---------------------------- */
+
+const char *sg_strerror(int code);
+const char *sg_last_error(void);   /* thread-local message of the last failure */
+const char *sg_version(void);
+
+/* beta schedule: kind 0 linear b0 + (b1-b0) s/(S-1); kind 1 geometric
+ * b0 (b1/b0)^(s/(S-1)); S == 1 gives b0.  beta_out: host double [S]. */
+int sg_make_schedule(int32_t kind, double b0, double b1, int32_t S, double *beta_out);
+
+/* Metropolis table: thr_out[s][k-1] = min(2^32-1, floor(exp(-(2k) beta_s) 2^32)),
+ * k = 1..K.  Host arrays beta [S], thr_out [S][K]. */
+int sg_make_thresholds(const double *beta, int32_t S, int32_t K, uint32_t *thr_out);
+
+/* Exchange table: thrx_out[k][m-1] = min(2^32-1, floor(exp(-(2m)(beta_{k+1}-beta_k)) 2^32)),
+ * m = 1..M.  Host arrays beta [T], thrx_out [T-1][M]. */
+int sg_make_exchange_thresholds(const double *beta, int32_t T, int32_t M, uint32_t *thrx_out);
+
+/* Smallest M for which the exchange table of the ladder has no nonzero
+ * entry cut off (the table is zero beyond). */
+int32_t sg_exchange_table_width(const double *beta, int32_t T);
+
+/* Synthetic tile-planted instance (a stand-in for the tile-planting model of
+ * Sec. II): unit cubes with even lower-corner parity are tiles; each draws
+ * twelve couplings in {-2,-1,1,2} until it has `cls` frustrated faces
+ * (cls in {0,2,4,6}; -1 = any); each tile is gauged so that all +1 is one
+ * of its ground states; bonds sum their two tiles; a random gauge hides
+ * the planted state.  Host outputs J [6][N], planted [N] (+-1), E_gs. */
+int sg_make_instance(int32_t L, int32_t cls, uint64_t seed, int8_t *J_host,
+                     int8_t *planted_host, int64_t *E_gs);
+
+/* ---- device helpers ------------------------------------------------------------ */
+
+/* Bytes of the encoded-coupling buffer used by the kernels for lattice L. */
+size_t sg_jenc_bytes(int32_t L);
+
+/* Fill inst->jenc-sized device buffer `jenc_out` from inst->J. */
+int sg_encode_instance(const sg_instance *inst, uint32_t *jenc_out, void *stream);
+
+/* Validate inst->J on the device: *status_out (device int32) receives 0 if
+ * every coupling lies in [-4, 4] and the two copies of every bond agree,
+ * otherwise 1 + the number of offending entries (saturating). */
+int sg_check_instance(const sg_instance *inst, int32_t *status_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,304 @@
+"""paper_2501_17267_amd -- Python binding of libsgmi (MI355X annealing of
+cubic-lattice Ising spin glasses).
+
+Argument marshalling only: every step of the annealing path runs in the HIP
+kernels of ``libsgmi.so`` behind the C ABI declared in ``include/sgmi.h``.
+PyTorch supplies device memory and the current stream.  The library must be
+built (``python -m paper_2501_17267_amd.build``); importing the binding
+without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgmi.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "sgmi.h")
+
+SG_OK = 0
+SG_MAX_L = 64
+SG_K_MAX = 24
+SG_LDS_MAX_L = 24
+SG_PT_MAX_T = 64
+
+
+class SgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class sg_instance(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("J", ctypes.c_void_p), ("jenc", ctypes.c_void_p),
+                ("E_gs", ctypes.c_int64), ("chain", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
+
+
+class sg_sa_args(ctypes.Structure):
+    _fields_ = [("n_rep", ctypes.c_int32), ("rep0", ctypes.c_uint32),
+                ("n_sweeps", ctypes.c_int32), ("sweep0", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("init_random", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class sg_pt_args(ctypes.Structure):
+    _fields_ = [("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
+                ("T", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("step0", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("init_random", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of every function the public header declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return [n for n in names if n not in ("defined",)]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsgmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2501_17267_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp = c.c_void_p
+    L.sg_strerror.restype = c.c_char_p
+    L.sg_strerror.argtypes = [c.c_int]
+    L.sg_last_error.restype = c.c_char_p
+    L.sg_last_error.argtypes = []
+    L.sg_version.restype = c.c_char_p
+    L.sg_make_schedule.argtypes = [c.c_int32, c.c_double, c.c_double, c.c_int32, vp]
+    L.sg_make_thresholds.argtypes = [vp, c.c_int32, c.c_int32, vp]
+    L.sg_make_exchange_thresholds.argtypes = [vp, c.c_int32, c.c_int32, vp]
+    L.sg_exchange_table_width.argtypes = [vp, c.c_int32]
+    L.sg_exchange_table_width.restype = c.c_int32
+    L.sg_make_instance.argtypes = [c.c_int32, c.c_int32, c.c_uint64, vp, vp, vp]
+    L.sg_jenc_bytes.restype = c.c_size_t
+    L.sg_jenc_bytes.argtypes = [c.c_int32]
+    L.sg_encode_instance.argtypes = [c.POINTER(sg_instance), vp, vp]
+    L.sg_check_instance.argtypes = [c.POINTER(sg_instance), vp, vp]
+    L.sa_anneal.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp, vp]
+    L.pt_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), vp, vp, vp, vp, vp, vp, vp, vp]
+    L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
+    L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
+    for fn in ("sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
+               "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal",
+               "pt_run", "energy", "epsilon"):
+        getattr(L, fn).restype = c.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != SG_OK:
+        msg = lib().sg_last_error().decode(errors="replace")
+        raise SgError(rc, f"{what}: {msg}")
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype_name: str):
+    if t is None:
+        return None
+    assert t.is_cuda, f"{dtype_name} tensor must live on the GPU"
+    assert t.is_contiguous(), f"{dtype_name} tensor must be contiguous"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# host helpers
+# ---------------------------------------------------------------------------
+
+def make_schedule(kind: int, b0: float, b1: float, S: int) -> np.ndarray:
+    out = np.zeros(S, np.float64)
+    _check(lib().sg_make_schedule(kind, b0, b1, S, _np_ptr(out)), "sg_make_schedule")
+    return out
+
+
+def make_thresholds(beta, K: int = SG_K_MAX) -> np.ndarray:
+    beta = np.ascontiguousarray(beta, np.float64)
+    out = np.zeros((len(beta), K), np.uint32)
+    _check(lib().sg_make_thresholds(_np_ptr(beta), len(beta), K, _np_ptr(out)), "sg_make_thresholds")
+    return out
+
+
+def make_exchange_thresholds(beta, M: int) -> np.ndarray:
+    beta = np.ascontiguousarray(beta, np.float64)
+    out = np.zeros((len(beta) - 1, M), np.uint32)
+    _check(lib().sg_make_exchange_thresholds(_np_ptr(beta), len(beta), M, _np_ptr(out)),
+           "sg_make_exchange_thresholds")
+    return out
+
+
+def exchange_table_width(beta) -> int:
+    beta = np.ascontiguousarray(beta, np.float64)
+    w = lib().sg_exchange_table_width(_np_ptr(beta), len(beta))
+    if w < 1:
+        _check(w, "sg_exchange_table_width")
+    return int(w)
+
+
+def make_instance(L: int, cls: int, seed: int):
+    """Host generator: returns (J int8 [6][N], planted int8 [N], E_gs)."""
+    N = L ** 3
+    J = np.zeros((6, N), np.int8)
+    g = np.zeros(N, np.int8)
+    egs = ctypes.c_int64(0)
+    _check(lib().sg_make_instance(L, cls, seed & 0xFFFFFFFFFFFFFFFF, _np_ptr(J), _np_ptr(g),
+                                  ctypes.addressof(egs)), "sg_make_instance")
+    return J, g, int(egs.value)
+
+
+def jenc_bytes(L: int) -> int:
+    return int(lib().sg_jenc_bytes(L))
+
+
+# ---------------------------------------------------------------------------
+# device-side wrappers
+# ---------------------------------------------------------------------------
+
+class Instance:
+    """An instance resident on the GPU: couplings J (torch int8 [6][N]),
+    optional encoded couplings, E_gs and its chain counter word."""
+
+    def __init__(self, L: int, J, E_gs: int, chain: int = 0, encode: bool | None = None,
+                 device="cuda"):
+        import torch
+        self.L = int(L)
+        self.E_gs = int(E_gs)
+        self.chain = int(chain)
+        if isinstance(J, np.ndarray):
+            J = torch.from_numpy(np.ascontiguousarray(J, np.int8))
+        self.J = J.to(device).contiguous()
+        self.jenc = None
+        if encode is None:
+            encode = self.L > SG_LDS_MAX_L
+        if encode:
+            self.jenc = torch.empty(jenc_bytes(self.L) // 4, dtype=torch.int32, device=self.J.device)
+            _check(lib().sg_encode_instance(ctypes.byref(self.struct(with_jenc=False)),
+                                            _dptr(self.jenc, "jenc"), _stream(None)),
+                   "sg_encode_instance")
+
+    @classmethod
+    def generate(cls, L: int, seed: int, chain: int = 0, klass: int = 6, **kw):
+        J, planted, egs = make_instance(L, klass, seed)
+        inst = cls(L, J, egs, chain, **kw)
+        inst.planted = planted
+        return inst
+
+    def struct(self, with_jenc: bool = True) -> sg_instance:
+        s = sg_instance()
+        s.L = self.L
+        s.J = self.J.data_ptr()
+        s.jenc = self.jenc.data_ptr() if (with_jenc and self.jenc is not None) else None
+        s.E_gs = self.E_gs
+        s.chain = self.chain & 0xFFFFFFFF
+        return s
+
+
+def check_instance(inst: Instance, stream=None) -> int:
+    import torch
+    st = torch.empty(1, dtype=torch.int32, device=inst.J.device)
+    _check(lib().sg_check_instance(ctypes.byref(inst.struct()), _dptr(st, "status"),
+                                   _stream(stream)), "sg_check_instance")
+    return int(st.item())
+
+
+def sa_anneal(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0: int = 0,
+              spins=None, want_emin: bool = False, stream=None, out=None):
+    """Anneal n_rep replicas with the threshold rows thr (torch uint32-as-int32
+    [n_sweeps][K] on the GPU).  spins=None draws them from the init stream.
+    Returns (spins int8 [n_rep][N], energy int32 [n_rep], emin or None)."""
+    import torch
+    dev = inst.J.device
+    N = inst.L ** 3
+    S, K = int(thr.shape[0]), int(thr.shape[1])
+    init_random = spins is None
+    if out is None:
+        sp = torch.empty((n_rep, N), dtype=torch.int8, device=dev) if init_random else spins
+        en = torch.empty(n_rep, dtype=torch.int32, device=dev)
+        em = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
+    else:
+        sp, en, em = out
+        if not init_random and sp.data_ptr() != spins.data_ptr():
+            sp.copy_(spins)
+    args = sg_sa_args(n_rep=n_rep, rep0=rep0, n_sweeps=S, sweep0=sweep0, K=K,
+                      init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _check(lib().sa_anneal(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                           _dptr(sp, "spins"), _dptr(en, "energy"), _dptr(em, "emin"),
+                           _stream(stream)), "sa_anneal")
+    return sp, en, em
+
+
+def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0: int = 0,
+           step0: int = 0, spins=None, pos=None, want_trace: bool = False,
+           want_swaps: bool = False, stream=None):
+    """Parallel tempering.  thr: device [T][K]; thrx: device [T-1][M].
+    Returns dict(spins [n_runs][T][N], energy [n_runs][T], pos [n_runs][T],
+    emin_trace, swap_acc)."""
+    import torch
+    dev = inst.J.device
+    N = inst.L ** 3
+    T, K = int(thr.shape[0]), int(thr.shape[1])
+    M = int(thrx.shape[1])
+    init_random = spins is None
+    sp = torch.empty((n_runs, T, N), dtype=torch.int8, device=dev) if init_random else spins
+    ps = torch.empty((n_runs, T), dtype=torch.int32, device=dev) if init_random else pos
+    en = torch.empty((n_runs, T), dtype=torch.int32, device=dev)
+    tr = torch.empty((n_runs, n_steps), dtype=torch.int32, device=dev) if want_trace else None
+    sw = torch.zeros((n_runs, T - 1), dtype=torch.int32, device=dev) if want_swaps else None
+    args = sg_pt_args(n_runs=n_runs, run0=run0, T=T, n_steps=n_steps, step0=step0, K=K, M=M,
+                      init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _check(lib().pt_run(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                        _dptr(thrx, "thrx"), _dptr(sp, "spins"), _dptr(en, "energy"),
+                        _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
+                        _stream(stream)), "pt_run")
+    return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+
+
+def energy(inst: Instance, spins, stream=None):
+    import torch
+    n = int(spins.shape[0])
+    out = torch.empty(n, dtype=torch.int32, device=spins.device)
+    _check(lib().energy(ctypes.byref(inst.struct()), n, _dptr(spins, "spins"), _dptr(out, "energy"),
+                        _stream(stream)), "energy")
+    return out
+
+
+def epsilon(energy_t, E_gs: int, stream=None):
+    import torch
+    n = int(energy_t.numel())
+    out = torch.empty(n, dtype=torch.float64, device=energy_t.device)
+    _check(lib().epsilon(_dptr(energy_t, "energy"), n, int(E_gs), _dptr(out, "eps"),
+                         _stream(stream)), "epsilon")
+    return out
+
+
+def to_device_u32(a: np.ndarray, device="cuda"):
+    """Upload a uint32 table (stored as int32 bits) to the GPU."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)

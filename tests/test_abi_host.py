@@ -1,0 +1,123 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, its host helpers (schedules, acceptance tables, the
+tile-planted generator) agree bit for bit with the oracle, and invalid
+arguments are refused before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_17267_amd as sg
+
+
+def test_library_exports_every_header_function():
+    lib = sg.lib()
+    names = sg.header_functions()
+    assert {"sa_anneal", "pt_run", "energy", "epsilon"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_and_version():
+    lib = sg.lib()
+    assert lib.sg_strerror(0) == b"ok"
+    assert lib.sg_strerror(-1) == b"invalid argument"
+    assert b"gfx950" in lib.sg_version()
+
+
+@pytest.mark.parametrize("kind,b0,b1,S", [(0, 0.1, 3.0, 1000), (0, 0.1, 3.0, 256), (1, 0.2, 3.0, 32),
+                                          (1, 0.3, 27.0, 977), (0, 5.0, 5.0, 3), (0, 0.7, 9.0, 1)])
+def test_schedule_and_thresholds_match_oracle(kind, b0, b1, S):
+    beta = sg.make_schedule(kind, b0, b1, S)
+    np.testing.assert_array_equal(beta, oracle.schedule(kind, b0, b1, S))
+    for K in (1, 6, 24):
+        np.testing.assert_array_equal(sg.make_thresholds(beta, K), oracle.thresholds(beta, K))
+
+
+def test_exchange_tables_match_oracle():
+    beta = sg.make_schedule(1, 0.2, 3.0, 32)
+    M = sg.exchange_table_width(beta)
+    assert M == 607
+    np.testing.assert_array_equal(sg.make_exchange_thresholds(beta, M), oracle.exchange_thresholds(beta, M))
+    ref = oracle.exchange_thresholds(beta, M + 50)
+    assert np.all(ref[:, M:] == 0)
+    assert np.any(ref[:, M - 1] != 0)
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12, 14, 16, 20, 24, 32])
+@pytest.mark.parametrize("cls", [6, 2, -1])
+def test_instance_generator_matches_oracle(L, cls):
+    seed = 0x9E37 * L + cls + 1000
+    J, g, egs = sg.make_instance(L, cls, seed)
+    Jo, go, egso = oracle.make_instance(L, cls, seed)
+    np.testing.assert_array_equal(J, Jo)
+    np.testing.assert_array_equal(g, go)
+    assert egs == egso
+
+
+def test_instance_generator_large_lattice_matches_oracle():
+    J, g, egs = sg.make_instance(64, 6, 12345)
+    Jo, go, egso = oracle.make_instance(64, 6, 12345)
+    np.testing.assert_array_equal(J, Jo)
+    assert egs == egso
+    assert oracle.energy(Jo, go, (64, 64, 64)) == egs
+
+
+def test_jenc_size():
+    for L in (4, 6, 12, 16, 64):
+        H, C = L // 2, (L + 3) // 4
+        assert sg.jenc_bytes(L) == 2 * (H * L) * 6 * 2 * C * 4
+    assert sg.jenc_bytes(5) == 0
+
+
+def _bad_call(fn, *args):
+    rc = fn(*args)
+    return rc, sg.lib().sg_last_error().decode()
+
+
+def test_invalid_arguments_are_refused_on_the_host():
+    lib = sg.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    inst = sg.sg_instance(L=5, J=0x1000, E_gs=-10)
+    args = sg.sg_sa_args(n_rep=4, n_sweeps=8, K=24, init_random=1, seed=1)
+    rc, msg = _bad_call(lib.sa_anneal, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None)
+    assert rc == -1 and "L = 5" in msg
+    inst.L = 8
+    args.K = 25
+    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -1
+    args.K = 24
+    args.n_rep = 0
+    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -1
+    args.n_rep = 4
+    args.sweep0 = (1 << 30)
+    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -4
+    args.sweep0 = 0
+    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, ctypes.c_void_p(0x1001), fake,
+                         None, None) == -1
+    assert lib.sa_anneal(None, ctypes.byref(args), fake, fake, fake, None, None) == -1
+    inst.L = 32
+    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -7
+    # PT
+    inst.L = 12
+    pargs = sg.sg_pt_args(n_runs=2, T=1, n_steps=5, K=24, M=10, init_random=1, seed=3)
+    assert lib.pt_run(ctypes.byref(inst), ctypes.byref(pargs), fake, fake, fake, fake, fake, None, None,
+                      None) == -1
+    pargs.T = 65
+    assert lib.pt_run(ctypes.byref(inst), ctypes.byref(pargs), fake, fake, fake, fake, fake, None, None,
+                      None) == -1
+    pargs.T = 8
+    pargs.M = 0
+    assert lib.pt_run(ctypes.byref(inst), ctypes.byref(pargs), fake, fake, fake, fake, fake, None, None,
+                      None) == -1
+    # energy / epsilon
+    assert lib.energy(ctypes.byref(inst), 0, fake, fake, None) == -1
+    assert lib.epsilon(fake, 10, 0, fake, None) == -1
+    assert lib.epsilon(fake, 0, -5, fake, None) == -1
+    # host helpers
+    out = np.zeros(4, np.float64)
+    assert lib.sg_make_schedule(1, 0.0, 3.0, 4, out.ctypes.data) == -1
+    assert lib.sg_make_schedule(0, 0.1, 3.0, 0, out.ctypes.data) == -1
+    thr = np.zeros(100, np.uint32)
+    assert lib.sg_make_thresholds(out.ctypes.data, 4, 25, thr.ctypes.data) == -1
+    assert lib.sg_make_instance(6, 3, 1, thr.ctypes.data, thr.ctypes.data, thr.ctypes.data) == -1
