@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the annealing hot path on one MI355X.
+
+A step is one pass of the whole path over the batched-SA workload:
+16 synthetic tile-planted instances at each of L = 8, 12, 16, 1024 replicas
+each, 256 sweeps with beta linear 0.1 -> 3.0 (initial spins drawn from the
+init stream, checkerboard Metropolis sweeps, final energies) followed by the
+optimality gap of every replica (Eq. 2).  Instances, schedules and tables are
+materialised before the timed region (their host cost is reported apart).
+
+Prints ONE JSON line: metric, value (spin-flip attempts/s), roofline of the
+dominant kernel, and the oracle timed on the host cores (cpu_baseline).
+
+  python bench.py [--steps K] [--warmup W] [--workload sa_batch|sa_small|pt|uneven]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts (CDNA4)
+N_CU = 256
+CLOCK_HZ = 2.4e9
+LANES_PER_CU = 64                      # 4 SIMD x 16 lanes, one 32-bit op each per clock
+VALU32_PEAK = N_CU * LANES_PER_CU * CLOCK_HZ   # 39.3 T 32-bit lane-ops/s
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic 32-bit integer operations per spin-flip attempt:
+#   Philox4x32-10 shared by 4 proposals: 10 rounds x (2 products x 2 halves
+#   + 2 three-input xors x 2) = 80 ops / 4 = 20
+#   local field: 6 products J*s plus 5 adds = 11
+#   acceptance: dE sign test, table compare, flip select = 3
+OPS_PER_ATTEMPT = 34
+# HBM bytes per attempt that the algorithm must move with whole lattices
+# resident on chip: none in the sweep; per anneal the couplings (6N), the
+# spins out (N) and the threshold rows -- reported as bytes per launch.
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "microbench"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--no-graph-compare", action="store_true",
+                    help="skip timing the same schedule replayed as a hipGraph")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def build_sa_batch(sg, wl, torch, graph=False):
+    w = wl.sa_batch()
+    t0 = time.perf_counter()
+    beta = sg.make_schedule(w.kind, w.beta0, w.beta1, w.n_sweeps)
+    thr_h = sg.make_thresholds(beta, sg.SG_K_MAX)
+    thr = sg.to_device_u32(thr_h)
+    insts = [sg.Instance.generate(s.L, s.seed, s.chain) for s in w.instances]
+    t_host = time.perf_counter() - t0
+    jobs = [sg.SAJob(inst, thr, w.n_rep, w.seed) for inst in insts]
+    batch = sg.Batch(jobs, graph=graph)
+    return w, insts, jobs, batch, thr_h, t_host
+
+
+def run_eps(sg, insts, jobs, eps_out):
+    for k, (inst, job) in enumerate(zip(insts, jobs)):
+        eps_out[k] = sg.epsilon(job.energy, inst.E_gs)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, unchanged, on a bounded sample of the workload
+# ---------------------------------------------------------------------------
+
+def cpu_baseline_sa(w, thr_h, target_s):
+    import concurrent.futures as cf
+
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    specs = {}
+    for s in w.instances:
+        specs.setdefault(s.L, s)
+    inst = {L: oracle.make_instance(L, s.cls, s.seed) for L, s in specs.items()}
+    # calibrate on one replica of the smallest lattice
+    Ls = sorted(specs)
+    t0 = time.perf_counter()
+    oracle.sa_run(Ls[0], inst[Ls[0]][0], w.seed, specs[Ls[0]].chain, thr_h, n_rep=1, rep0=0)
+    per_att = (time.perf_counter() - t0) / (w.n_sweeps * Ls[0] ** 3)
+    # replicas per size so that all sizes together take ~target_s on `cores` threads
+    att_budget = target_s * cores / per_att
+    per_size = att_budget / len(Ls)
+    tasks = []
+    for L in Ls:
+        n = max(1, int(per_size / (w.n_sweeps * L ** 3)))
+        n = min(n, w.n_rep)
+        tasks += [(L, r) for r in range(n)]
+
+    def one(task):
+        L, r = task
+        oracle.sa_run(L, inst[L][0], w.seed, specs[L].chain, thr_h, n_rep=1, rep0=r)
+        return w.n_sweeps * L ** 3
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        attempts = sum(ex.map(one, tasks))
+    dt = time.perf_counter() - t0
+    counts = {L: sum(1 for t in tasks if t[0] == L) for L in Ls}
+    sample = ", ".join(f"L={L}: {counts[L]} replicas" for L in Ls)
+    return {"value": attempts / dt, "unit": "spin-flip attempts/s", "cores": cores, "kind": "oracle",
+            "sample": f"first instance of each size, {sample}, {w.n_sweeps} sweeps each "
+                      f"({attempts:.3g} attempts in {dt:.1f} s)"}
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2501_17267_amd as sg
+    from paper_2501_17267_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    if a.workload != "sa_batch":
+        from paper_2501_17267_amd import benchmarks
+        out = benchmarks.run(a.workload, a, sg, wl, torch)
+        print(json.dumps(out))
+        return
+
+    # direct launches: per-kernel timing events are recorded on each branch
+    w, insts, jobs, batch, thr_h, t_host = build_sa_batch(sg, wl, torch, graph=False)
+    info = batch.info()
+    attempts = info["attempts"]
+    log(f"sa_batch: {len(insts)} instances, {info['kernels']} kernels, {info['groups']} groups, "
+        f"{attempts:.4g} attempts/step; host set-up {t_host:.2f} s")
+    eps = [None] * len(insts)
+
+    def step():
+        batch.launch(stream)
+        run_eps(sg, insts, jobs, eps)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kernel_ms = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        step()
+        # per-kernel device times of this launch (events recorded inside the
+        # replayed graph on each branch stream)
+        torch.cuda.synchronize()
+        for k in batch.kernels():
+            kernel_ms.setdefault(k["L"], []).append(k["ms"])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = dev_ms / a.steps
+    value = attempts / (ms_per_step * 1e-3)
+
+    graph_ms = None
+    if not a.no_graph_compare:
+        gbatch = sg.Batch(jobs, graph=True)
+
+        def gstep():
+            gbatch.launch(stream)
+            run_eps(sg, insts, jobs, eps)
+        for _ in range(a.warmup):
+            gstep()
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(a.steps):
+            gstep()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / a.steps
+        gbatch.close()
+
+    # quality (not timed): eps distribution of the last step
+    all_eps = torch.cat(eps).cpu().numpy()
+    kern = batch.kernels()
+    dom = max(kern, key=lambda k: float(np.mean(kernel_ms[k["L"]])))
+    dom_ms = float(np.mean(kernel_ms[dom["L"]]))
+    achieved = dom["attempts"] * OPS_PER_ATTEMPT / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU32_PEAK / 1e12,
+                "unit": "Tops/s (32-bit integer lane-ops)", "frac": achieved / VALU32_PEAK,
+                "traffic": None, "kernel": f"k_sa_batch L={dom['L']}",
+                "kernel_ms": dom_ms, "ops_per_attempt": OPS_PER_ATTEMPT,
+                "attempts_per_launch": dom["attempts"]}
+    out = {
+        "metric": "spin-flip attempts/s (batched SA, 48 instances L=8/12/16 x 1024 replicas x 256 sweeps)",
+        "value": value, "unit": "spin-flip attempts/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "sa_batch: 16 tile-planted T6 instances at each of L=8,12,16, "
+                               "1024 replicas, 256 sweeps, beta linear 0.1->3.0",
+                   "instances": len(insts), "replicas": w.n_rep, "sweeps": w.n_sweeps,
+                   "attempts_per_step": attempts, "launch": "3 kernels (one per L) on parallel streams"},
+        "graph_replay": None if graph_ms is None else {"ms_per_step": graph_ms,
+                                                       "attempts_per_s": attempts / (graph_ms * 1e-3)},
+        "roofline": roofline,
+        "kernels": [{"L": k["L"], "ms": float(np.mean(kernel_ms[k["L"]])), "attempts": k["attempts"],
+                     "attempts_per_s": k["attempts"] / (float(np.mean(kernel_ms[k["L"]])) * 1e-3)}
+                    for k in kern],
+        "eps": {"mean": float(all_eps.mean()), "min": float(all_eps.min()),
+                "p50": float(np.median(all_eps)), "frac_le_1pct": float(np.mean(all_eps <= 0.01))},
+        "host_setup_s": t_host, "wall_s": wall,
+    }
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_sa(w, thr_h, a.cpu_seconds)
+    batch.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,42 @@ int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t 
  * from exact integers.  energy and eps_out are device arrays of n entries. */
 int epsilon(const int32_t *energy, int64_t n, int64_t E_gs, double *eps_out, void *stream);
 
+/* ---- batched annealing ----------------------------------------------------------
+ * Many sa_anneal calls (instances of different L, replica counts and sweep
+ * budgets) fused into one schedule.  Each job keeps exactly the semantics
+ * of the sa_anneal call it describes: results are bit-identical to running
+ * the jobs one by one, in any order.  The plan groups jobs by L, orders each
+ * group's work longest first, uploads the job tables to device memory it
+ * owns, and launches one kernel per L on parallel branches; with
+ * SG_BATCH_GRAPH the whole schedule is captured once as a hipGraph and each
+ * sg_batch_launch replays it.  A plan stores the jobs' device pointers:
+ * they must stay valid while the plan is launched. */
+typedef struct sg_sa_job {
+    sg_instance inst;
+    sg_sa_args args;
+    const uint32_t *thr;   /* device [n_sweeps][K] */
+    int8_t *spins;         /* device [n_rep][N] */
+    int32_t *energy;       /* device [n_rep] */
+    int32_t *emin;         /* device [n_rep] or NULL */
+} sg_sa_job;
+
+typedef struct sg_batch sg_batch;
+
+#define SG_BATCH_GRAPH 1   /* capture the schedule as a hipGraph */
+
+int sg_batch_create(const sg_sa_job *jobs, int32_t n_jobs, int32_t flags, sg_batch **out);
+int sg_batch_launch(sg_batch *batch, void *stream);
+/* n_kernels: kernels per launch; attempts: spin-flip attempts per launch */
+int sg_batch_info(const sg_batch *batch, int32_t *n_kernels, int64_t *n_groups, double *attempts);
+/* Per-kernel view of the plan, one entry per lattice size (up to n):
+ * L, spin-flip attempts per launch, and the device time in ms of that
+ * kernel in the most recent completed launch (-1 if unavailable).
+ * Returns the number of entries written. */
+int sg_batch_kernels(const sg_batch *batch, int32_t n, int32_t *L_out, double *attempts_out,
+                     float *ms_out);
+/* waits for the plan's work to finish, then frees it */
+int sg_batch_destroy(sg_batch *batch);
+
 /* ---- host helpers (synchronous, no device work) ---------------------------- */
 
 const char *sg_strerror(int code);

@@ -46,6 +46,11 @@ class sg_sa_args(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class sg_sa_job(ctypes.Structure):
+    _fields_ = [("inst", sg_instance), ("args", sg_sa_args), ("thr", ctypes.c_void_p),
+                ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("emin", ctypes.c_void_p)]
+
+
 class sg_pt_args(ctypes.Structure):
     _fields_ = [("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
                 ("T", ctypes.c_int32), ("n_steps", ctypes.c_int32),
@@ -95,7 +100,13 @@ def lib() -> ctypes.CDLL:
     L.pt_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), vp, vp, vp, vp, vp, vp, vp, vp]
     L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
     L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
-    for fn in ("sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
+    L.sg_batch_create.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
+    L.sg_batch_launch.argtypes = [vp, vp]
+    L.sg_batch_info.argtypes = [vp, vp, vp, vp]
+    L.sg_batch_kernels.argtypes = [vp, c.c_int32, vp, vp, vp]
+    L.sg_batch_destroy.argtypes = [vp]
+    for fn in ("sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
+               "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal",
                "pt_run", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
@@ -302,3 +313,78 @@ def to_device_u32(a: np.ndarray, device="cuda"):
     """Upload a uint32 table (stored as int32 bits) to the GPU."""
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(device)
+
+
+SG_BATCH_GRAPH = 1
+
+
+class SAJob:
+    """One sa_anneal call described for a batch: the instance, its replica
+    range and schedule, and the output buffers (allocated here)."""
+
+    def __init__(self, inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0: int = 0,
+                 spins=None, want_emin: bool = False):
+        import torch
+        dev = inst.J.device
+        self.inst, self.thr, self.n_rep = inst, thr, n_rep
+        self.seed, self.rep0, self.sweep0 = seed, rep0, sweep0
+        self.init_random = spins is None
+        self.spins = torch.empty((n_rep, inst.L ** 3), dtype=torch.int8, device=dev) if spins is None else spins
+        self.energy = torch.empty(n_rep, dtype=torch.int32, device=dev)
+        self.emin = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
+
+    def struct(self) -> sg_sa_job:
+        j = sg_sa_job()
+        j.inst = self.inst.struct()
+        j.args = sg_sa_args(n_rep=self.n_rep, rep0=self.rep0, n_sweeps=int(self.thr.shape[0]),
+                            sweep0=self.sweep0, K=int(self.thr.shape[1]),
+                            init_random=1 if self.init_random else 0,
+                            seed=self.seed & 0xFFFFFFFFFFFFFFFF)
+        j.thr = self.thr.data_ptr()
+        j.spins = self.spins.data_ptr()
+        j.energy = self.energy.data_ptr()
+        j.emin = self.emin.data_ptr() if self.emin is not None else None
+        return j
+
+
+class Batch:
+    """A batched annealing plan (sg_batch_*): jobs grouped by L, one kernel
+    per L on parallel branches, optionally replayed as a hipGraph."""
+
+    def __init__(self, jobs: list, graph: bool = True):
+        self.jobs = list(jobs)   # keeps the device buffers alive
+        arr = (sg_sa_job * len(self.jobs))(*[j.struct() for j in self.jobs])
+        h = ctypes.c_void_p()
+        _check(lib().sg_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.jobs),
+                                     SG_BATCH_GRAPH if graph else 0, ctypes.byref(h)), "sg_batch_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().sg_batch_launch(self.handle, _stream(stream)), "sg_batch_launch")
+
+    def info(self):
+        nk = ctypes.c_int32()
+        ng = ctypes.c_int64()
+        att = ctypes.c_double()
+        _check(lib().sg_batch_info(self.handle, ctypes.byref(nk), ctypes.byref(ng), ctypes.byref(att)),
+               "sg_batch_info")
+        return {"kernels": nk.value, "groups": ng.value, "attempts": att.value}
+
+    def kernels(self):
+        n = 64
+        Ls = np.zeros(n, np.int32)
+        att = np.zeros(n, np.float64)
+        ms = np.zeros(n, np.float32)
+        m = lib().sg_batch_kernels(self.handle, n, _np_ptr(Ls), _np_ptr(att), _np_ptr(ms))
+        return [{"L": int(Ls[i]), "attempts": float(att[i]), "ms": float(ms[i])} for i in range(m)]
+
+    def close(self):
+        if self.handle:
+            lib().sg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,119 @@
+"""Secondary benchmark modes of bench.py (one JSON object each).
+
+  microbench  VALU instruction throughput probes (the ALU ceiling's inputs)
+  sa_small    one L=4 instance, 64 restarts x 1000 sweeps
+  plain       the batched-SA workload issued as 48 separate sa_anneal calls
+  pt          parallel tempering: L=12, 32 temperatures, 128 runs x 2000 steps
+  uneven      4096 instances of mixed L and sweep budget: batch vs plain calls
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+
+import numpy as np
+
+N_CU = 256
+CLOCK_HZ = 2.4e9
+VALU32_PEAK = N_CU * 64 * CLOCK_HZ
+
+
+def _time(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def microbench(a, sg, wl, torch):
+    lib = sg.lib()
+    lib.sg_microbench_valu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    lib.sg_microbench_valu.restype = ctypes.c_int
+    stream = torch.cuda.current_stream()
+    blocks, iters = 256 * 16, 4096
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    names = ["v_mad_u64_u32", "xor3", "add3", "bitfield select"]
+    res = {}
+    for op in range(4):
+        def fn():
+            rc = lib.sg_microbench_valu(op, blocks, iters, out.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+            assert rc == 0
+        ms = _time(torch, fn, 5, 2, stream)
+        instr = blocks * 256 * iters * 8.0
+        rate = instr / (ms * 1e-3)
+        res[names[op]] = {"lane_ops_per_s": rate, "frac_of_full_rate": rate / VALU32_PEAK,
+                          "ms": ms}
+    return {"metric": "VALU instruction throughput", "unit": "lane-ops/s",
+            "peak_full_rate": VALU32_PEAK, "probes": res}
+
+
+def sa_small(a, sg, wl, torch):
+    w = wl.sa_small()
+    spec = w.instances[0]
+    inst = sg.Instance.generate(spec.L, spec.seed, spec.chain)
+    thr = sg.to_device_u32(sg.make_thresholds(sg.make_schedule(w.kind, w.beta0, w.beta1, w.n_sweeps)))
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def fn():
+        res["out"] = sg.sa_anneal(inst, thr, w.n_rep, w.seed)
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    att = w.n_rep * w.n_sweeps * spec.L ** 3
+    eps = sg.epsilon(res["out"][1], inst.E_gs).cpu().numpy()
+    return {"metric": "spin-flip attempts/s (L=4, 64 restarts x 1000 sweeps)", "value": att / (ms * 1e-3),
+            "unit": "spin-flip attempts/s", "ms_per_step": ms, "eps_mean": float(eps.mean()),
+            "eps_min": float(eps.min()), "frac_at_gs": float(np.mean(eps == 0.0))}
+
+
+def plain(a, sg, wl, torch):
+    """The batched workload as 48 plain per-instance calls on one stream."""
+    w = wl.sa_batch()
+    beta = sg.make_schedule(w.kind, w.beta0, w.beta1, w.n_sweeps)
+    thr = sg.to_device_u32(sg.make_thresholds(beta))
+    insts = [sg.Instance.generate(s.L, s.seed, s.chain) for s in w.instances]
+    outs = [(torch.empty((w.n_rep, i.L ** 3), dtype=torch.int8, device="cuda"),
+             torch.empty(w.n_rep, dtype=torch.int32, device="cuda"), None) for i in insts]
+    stream = torch.cuda.current_stream()
+
+    def fn():
+        for inst, o in zip(insts, outs):
+            sg.sa_anneal(inst, thr, w.n_rep, w.seed, out=o)
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    att = sum(w.n_rep * w.n_sweeps * i.L ** 3 for i in insts)
+    return {"metric": "spin-flip attempts/s (48 plain sa_anneal calls)", "value": att / (ms * 1e-3),
+            "unit": "spin-flip attempts/s", "ms_per_step": ms}
+
+
+def pt(a, sg, wl, torch):
+    w = wl.pt()
+    inst = sg.Instance.generate(w.instance.L, w.instance.seed, 0)
+    beta = sg.make_schedule(1, w.beta0, w.beta1, w.T)
+    thr = sg.to_device_u32(sg.make_thresholds(beta))
+    M = sg.exchange_table_width(beta)
+    thrx = sg.to_device_u32(sg.make_exchange_thresholds(beta, M))
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def fn():
+        res["out"] = sg.pt_run(inst, thr, thrx, w.n_runs, w.n_steps, w.seed, want_trace=True)
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    att = w.n_runs * w.n_steps * w.T * w.instance.L ** 3
+    final_min = res["out"]["emin_trace"][:, -1].cpu().numpy().astype(np.int64)
+    eps = (final_min - inst.E_gs) / abs(inst.E_gs)
+    return {"metric": "spin-flip attempts/s (PT L=12, T=32, 128 runs x 2000 steps)",
+            "value": att / (ms * 1e-3), "unit": "spin-flip attempts/s", "ms_per_step": ms,
+            "exchange_attempts_per_step": w.n_runs * w.n_steps * (w.T - 1) / 2,
+            "eps_best_mean": float(eps.mean()), "eps_best_min": float(eps.min())}
+
+
+def run(name, a, sg, wl, torch):
+    fn = {"microbench": microbench, "sa_small": sa_small, "plain": plain, "pt": pt}[name]
+    return fn(a, sg, wl, torch)

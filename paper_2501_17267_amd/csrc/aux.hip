@@ -127,6 +127,7 @@ int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t 
     if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "energy: L = %d", inst->L);
     if (n_rep < 1) return fail(SG_EINVAL, "energy: n_rep = %d", n_rep);
     clear_error();
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_energy, dim3(n_rep), dim3(kEnergyThreads), 0, static_cast<hipStream_t>(stream),
                        inst->J, inst->L, spins, energy_out);
     return check_launch("energy");
@@ -140,6 +141,7 @@ int epsilon(const int32_t *energy_in, int64_t n, int64_t E_gs, double *eps_out, 
     clear_error();
     const int threads = 256;
     const int64_t blocks = (n + threads - 1) / threads;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_epsilon, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0,
                        static_cast<hipStream_t>(stream), energy_in, n, E_gs, eps_out);
     return check_launch("epsilon");
@@ -159,6 +161,7 @@ int sg_encode_instance(const sg_instance *inst, uint32_t *jenc_out, void *stream
     clear_error();
     const int64_t total = static_cast<int64_t>(sg_jenc_bytes(inst->L) / sizeof(uint32_t));
     const int threads = 256;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_encode, dim3(static_cast<unsigned>((total + threads - 1) / threads)), dim3(threads), 0,
                        static_cast<hipStream_t>(stream), inst->J, inst->L, jenc_out);
     return check_launch("sg_encode_instance");
@@ -171,6 +174,7 @@ int sg_check_instance(const sg_instance *inst, int32_t *status_out, void *stream
     clear_error();
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t N = static_cast<int64_t>(inst->L) * inst->L * inst->L;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, st, status_out, 0);
     hipLaunchKernelGGL(k_check, dim3(static_cast<unsigned>((N + 255) / 256)), dim3(256), 0, st, inst->J, inst->L,
                        status_out);

@@ -179,6 +179,7 @@ static int launch_pt(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hip
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: LDS attribute: %s", hipGetErrorString(err));
+    (void)hipGetLastError();
     hipLaunchKernelGGL(kern, dim3(n_runs), dim3(Cfg::NW * 64), bytes, stream, job, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: launch failed: %s", hipGetErrorString(err));

@@ -22,6 +22,7 @@ template <int L, int RPW, int NW, bool JF>
 static int launch_sa(const SaJob &job, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
     const int groups = (job.n_rep + RPW - 1) / RPW;
+    (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
     if (job.emin)
         hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, true>), dim3(groups), dim3(NW * 64), 0, stream, job, k0, k1);
     else

@@ -22,6 +22,7 @@ struct SaJob {
     int32_t K;
     int32_t init_random;
     int32_t pad;
+    uint32_t k0, k1;        // Philox key (batched launches)
 };
 
 // Launch shape per lattice size: RPW replicas per group, NW waves, JF =
@@ -152,7 +153,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     __syncthreads();
     if (tid < nact) {
         job.energy[r_first + tid] = s_dE[0][tid];
-        if (track) job.emin[r_first + tid] = best;
+        if (track && job.emin) job.emin[r_first + tid] = best;
     }
 }
 
