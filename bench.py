@@ -54,9 +54,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "microbench"])
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "microbench", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--no-graph-compare", action="store_true",
                     help="skip timing the same schedule replayed as a hipGraph")
     return ap.parse_args()
@@ -151,6 +152,15 @@ def main():
         print(json.dumps(out))
         return
 
+    tuning = {}
+    if not a.no_autotune:
+        # launch shapes chosen on the device before the timed region
+        for L in sorted({s.L for s in wl.sa_batch().instances}):
+            res = sg.autotune(L, n_rep=16384, n_sweeps=32, repeats=2)
+            v = res["selected"]
+            tuning[L] = {"variant": v, **sg.sa_variants(L)[v],
+                         "candidates_ms": [round(r["ms"], 4) for r in res["results"]]}
+            log(f"autotune L={L}: variant {v} {tuning[L]}")
     # direct launches: per-kernel timing events are recorded on each branch
     w, insts, jobs, batch, thr_h, t_host = build_sa_batch(sg, wl, torch, graph=False)
     info = batch.info()
@@ -234,7 +244,7 @@ def main():
                     for k in kern],
         "eps": {"mean": float(all_eps.mean()), "min": float(all_eps.min()),
                 "p50": float(np.median(all_eps)), "frac_le_1pct": float(np.mean(all_eps <= 0.01))},
-        "host_setup_s": t_host, "wall_s": wall,
+        "host_setup_s": t_host, "wall_s": wall, "launch_shapes": tuning,
     }
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

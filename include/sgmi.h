@@ -145,6 +145,44 @@ int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t 
  * from exact integers.  energy and eps_out are device arrays of n entries. */
 int epsilon(const int32_t *energy, int64_t n, int64_t E_gs, double *eps_out, void *stream);
 
+/* ---- launch shapes and autotuning -----------------------------------------------
+ * The annealing kernel exists in several launch shapes per lattice size
+ * ("variants": replicas per work group, waves per work group, whether LDS
+ * holds both coupling encodings).  All produce bit-identical results; they
+ * differ only in speed.  sa_anneal and new batch plans use the selected
+ * variant of each size (the first one until a selection or autotune). */
+typedef struct sg_sa_variant {
+    int32_t L;
+    int32_t replicas_per_group;
+    int32_t waves_per_group;
+    int32_t both_encodings;   /* 1: E and F coupling encodings in LDS; 0: E only */
+    int64_t lds_bytes;        /* LDS per work group */
+} sg_sa_variant;
+
+typedef struct sg_sa_tune_result {
+    int32_t variant;
+    int32_t identical;        /* 1 if its output equalled variant 0's bit for bit */
+    float ms;                 /* mean device time of one call */
+    double attempts_per_s;
+} sg_sa_tune_result;
+
+/* Writes up to max variants of size L into out; returns the count. */
+int sg_sa_variants(int32_t L, int32_t max, sg_sa_variant *out);
+int sg_sa_select_variant(int32_t L, int32_t variant);
+/* selected variant index of size L (or a negative status) */
+int sg_sa_selected_variant(int32_t L);
+/* sa_anneal with an explicit variant */
+int sg_sa_anneal_variant(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
+                         int8_t *spins, int32_t *energy, int32_t *emin, int32_t variant,
+                         void *stream);
+/* Autotuner: anneals one synthetic instance of size L (n_rep replicas,
+ * n_sweeps sweeps, beta linear 0.1 -> 3.0) with every variant, `repeats`
+ * timed calls each, checks that all outputs are bit-identical, selects the
+ * fastest and returns its index.  Fills out[0..max_out) with the timings.
+ * Allocates and frees its own device buffers; synchronous. */
+int sg_autotune_sa(int32_t L, int32_t n_rep, int32_t n_sweeps, int32_t repeats,
+                   sg_sa_tune_result *out, int32_t max_out, void *stream);
+
 /* ---- batched annealing ----------------------------------------------------------
  * Many sa_anneal calls (instances of different L, replica counts and sweep
  * budgets) fused into one schedule.  Each job keeps exactly the semantics

@@ -19,6 +19,11 @@ extern "C" {
  * work cannot be elided.  Time it with events around the call. */
 int sg_microbench_valu(int32_t op, int32_t blocks, int32_t iters, uint32_t *out, void *stream);
 
+/* Plain streaming copy of `bytes` (a multiple of 16) from src to dst (device
+ * buffers): the reference kernel for converting HBM byte counters
+ * (FETCH_SIZE, WRITE_SIZE) into bytes. */
+int sg_microbench_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,17 @@ class sg_sa_job(ctypes.Structure):
                 ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("emin", ctypes.c_void_p)]
 
 
+class sg_sa_variant(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("replicas_per_group", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("both_encodings", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64)]
+
+
+class sg_sa_tune_result(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("identical", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("attempts_per_s", ctypes.c_double)]
+
+
 class sg_pt_args(ctypes.Structure):
     _fields_ = [("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
                 ("T", ctypes.c_int32), ("n_steps", ctypes.c_int32),
@@ -105,7 +116,14 @@ def lib() -> ctypes.CDLL:
     L.sg_batch_info.argtypes = [vp, vp, vp, vp]
     L.sg_batch_kernels.argtypes = [vp, c.c_int32, vp, vp, vp]
     L.sg_batch_destroy.argtypes = [vp]
-    for fn in ("sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
+    L.sg_sa_variants.argtypes = [c.c_int32, c.c_int32, vp]
+    L.sg_sa_select_variant.argtypes = [c.c_int32, c.c_int32]
+    L.sg_sa_selected_variant.argtypes = [c.c_int32]
+    L.sg_sa_anneal_variant.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp,
+                                       c.c_int32, vp]
+    L.sg_autotune_sa.argtypes = [c.c_int32, c.c_int32, c.c_int32, c.c_int32, vp, c.c_int32, vp]
+    for fn in ("sg_sa_variants", "sg_sa_select_variant", "sg_sa_selected_variant",
+               "sg_sa_anneal_variant", "sg_autotune_sa", "sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal",
                "pt_run", "energy", "epsilon"):
@@ -289,6 +307,75 @@ def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0
                         _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
                         _stream(stream)), "pt_run")
     return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+
+
+def sa_variants(L: int) -> list[dict]:
+    buf = (sg_sa_variant * 16)()
+    n = lib().sg_sa_variants(L, 16, ctypes.cast(buf, ctypes.c_void_p))
+    if n < 0:
+        _check(n, "sg_sa_variants")
+    return [{"L": buf[i].L, "replicas_per_group": buf[i].replicas_per_group,
+             "waves_per_group": buf[i].waves_per_group, "both_encodings": bool(buf[i].both_encodings),
+             "lds_bytes": buf[i].lds_bytes} for i in range(n)]
+
+
+def select_variant(L: int, variant: int) -> None:
+    _check(lib().sg_sa_select_variant(L, variant), "sg_sa_select_variant")
+
+
+def selected_variant(L: int) -> int:
+    v = lib().sg_sa_selected_variant(L)
+    if v < 0:
+        _check(v, "sg_sa_selected_variant")
+    return v
+
+
+def sa_anneal_variant(inst: Instance, thr, n_rep: int, seed: int, variant: int, rep0: int = 0,
+                      sweep0: int = 0, spins=None, want_emin: bool = False, stream=None):
+    """sa_anneal with an explicit launch-shape variant (results are identical)."""
+    import torch
+    dev = inst.J.device
+    N = inst.L ** 3
+    S, K = int(thr.shape[0]), int(thr.shape[1])
+    init_random = spins is None
+    sp = torch.empty((n_rep, N), dtype=torch.int8, device=dev) if init_random else spins
+    en = torch.empty(n_rep, dtype=torch.int32, device=dev)
+    em = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
+    args = sg_sa_args(n_rep=n_rep, rep0=rep0, n_sweeps=S, sweep0=sweep0, K=K,
+                      init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _check(lib().sg_sa_anneal_variant(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                                      _dptr(sp, "spins"), _dptr(en, "energy"), _dptr(em, "emin"),
+                                      variant, _stream(stream)), "sg_sa_anneal_variant")
+    return sp, en, em
+
+
+def autotune(L: int, n_rep: int = 4096, n_sweeps: int = 32, repeats: int = 3, stream=None) -> dict:
+    """Time every launch shape of size L, check they agree bit for bit,
+    select the fastest.  Returns {"selected": i, "results": [...]}."""
+    buf = (sg_sa_tune_result * 16)()
+    r = lib().sg_autotune_sa(L, n_rep, n_sweeps, repeats, ctypes.cast(buf, ctypes.c_void_p), 16,
+                             _stream(stream))
+    if r < 0:
+        _check(r, "sg_autotune_sa")
+    nv = len(sa_variants(L))
+    return {"selected": int(r), "results": [{"variant": buf[i].variant, "identical": bool(buf[i].identical),
+                                              "ms": float(buf[i].ms), "attempts_per_s": buf[i].attempts_per_s}
+                                             for i in range(nv)]}
+
+
+def save_tuning(path: str, Ls) -> None:
+    import json
+    with open(path, "w") as f:
+        json.dump({str(L): selected_variant(L) for L in Ls}, f)
+
+
+def load_tuning(path: str) -> dict:
+    import json
+    with open(path) as f:
+        choice = {int(k): int(v) for k, v in json.load(f).items()}
+    for L, v in choice.items():
+        select_variant(L, v)
+    return choice
 
 
 def energy(inst: Instance, spins, stream=None):

@@ -55,6 +55,25 @@ def microbench(a, sg, wl, torch):
             "peak_full_rate": VALU32_PEAK, "probes": res}
 
 
+def copy(a, sg, wl, torch):
+    """A 256 MiB device-to-device copy with the library's plain copy kernel."""
+    lib = sg.lib()
+    lib.sg_microbench_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.sg_microbench_copy.restype = ctypes.c_int
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+
+    def fn():
+        rc = lib.sg_microbench_copy(src.data_ptr(), dst.data_ptr(), nbytes, ctypes.c_void_p(stream.cuda_stream))
+        assert rc == 0
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    assert bool((dst == 1).all())
+    return {"metric": "device copy bandwidth", "bytes_read": nbytes, "bytes_written": nbytes,
+            "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def sa_small(a, sg, wl, torch):
     w = wl.sa_small()
     spec = w.instances[0]
@@ -115,5 +134,5 @@ def pt(a, sg, wl, torch):
 
 
 def run(name, a, sg, wl, torch):
-    fn = {"microbench": microbench, "sa_small": sa_small, "plain": plain, "pt": pt}[name]
+    fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt}[name]
     return fn(a, sg, wl, torch)

@@ -6,62 +6,12 @@
 #include <vector>
 
 #include "common.hpp"
-#include "sa_kernel.hpp"
+#include "variants.hpp"
 
 namespace sg {
 
-struct Group {
-    int32_t job;    // index into the bucket's job table
-    int32_t group;  // replica group inside the job
-};
-
-template <int L, int RPW, int NW, bool JF, bool TRACK>
-__global__ __launch_bounds__(NW * 64) void k_sa_batch(const SaJob *jobs, const Group *groups)
-{
-    const Group g = groups[blockIdx.x];
-    const SaJob job = jobs[g.job];
-    sa_group<L, RPW, NW, JF, TRACK>(job, g.group, job.k0, job.k1);
-}
-
-template <int L>
-static int launch_bucket(const SaJob *d_jobs, const Group *d_groups, int n_groups, bool track, hipStream_t st)
-{
-    using Cfg = SaCfg<L>;
-    (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
-    if (track)
-        hipLaunchKernelGGL((k_sa_batch<L, Cfg::RPW, Cfg::NW, Cfg::JF, true>), dim3(n_groups), dim3(Cfg::NW * 64), 0,
-                           st, d_jobs, d_groups);
-    else
-        hipLaunchKernelGGL((k_sa_batch<L, Cfg::RPW, Cfg::NW, Cfg::JF, false>), dim3(n_groups), dim3(Cfg::NW * 64),
-                           0, st, d_jobs, d_groups);
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return fail(SG_EDEVICE, "sg_batch_launch: %s", hipGetErrorString(err));
-    return SG_OK;
-}
-
-static int replicas_per_group(int L)
-{
-    switch (L) {
-#define SG_RPW(LL) \
-    case LL: return SaCfg<LL>::RPW;
-        SG_RPW(4) SG_RPW(6) SG_RPW(8) SG_RPW(10) SG_RPW(12) SG_RPW(14) SG_RPW(16) SG_RPW(18) SG_RPW(20)
-        SG_RPW(22) SG_RPW(24)
-#undef SG_RPW
-    default: return 0;
-    }
-}
-
-static int launch_bucket_any(int L, const SaJob *j, const Group *g, int n, bool track, hipStream_t st)
-{
-    switch (L) {
-#define SG_BK(LL) \
-    case LL: return launch_bucket<LL>(j, g, n, track, st);
-        SG_BK(4) SG_BK(6) SG_BK(8) SG_BK(10) SG_BK(12) SG_BK(14) SG_BK(16) SG_BK(18) SG_BK(20) SG_BK(22)
-        SG_BK(24)
-#undef SG_BK
-    default: return fail(SG_EUNSUPPORTED, "sg_batch: L = %d", L);
-    }
-}
+int sa_check_job(const sg_sa_job &j, int index);
+void sa_fill_job(SaJob &job, const sg_sa_job &j);
 
 }  // namespace sg
 
@@ -70,6 +20,8 @@ using namespace sg;
 struct sg_batch {
     struct Bucket {
         int L = 0;
+        int variant = 0;
+        const SaVariant *v = nullptr;
         bool track = false;
         int n_groups = 0;
         SaJob *d_jobs = nullptr;
@@ -117,7 +69,8 @@ struct sg_batch {
             // recorded inside a captured graph cannot be queried)
             if (!capturing && hipEventRecord(b.t0, b.stream) != hipSuccess)
                 return fail(SG_EDEVICE, "sg_batch: event record");
-            const int rc = launch_bucket_any(b.L, b.d_jobs, b.d_groups, b.n_groups, b.track, b.stream);
+            const SaJob none{};
+            const int rc = b.v->launch(b.d_jobs, b.d_groups, none, b.n_groups, b.track, b.stream);
             if (rc != SG_OK) return rc;
             if (!capturing && hipEventRecord(b.t1, b.stream) != hipSuccess)
                 return fail(SG_EDEVICE, "sg_batch: event record");
@@ -136,19 +89,9 @@ int sg_batch_create(const sg_sa_job *jobs, int32_t n_jobs, int32_t flags, sg_bat
     *out = nullptr;
     std::map<int, std::vector<int>> by_L;
     for (int32_t i = 0; i < n_jobs; ++i) {
-        const sg_sa_job &j = jobs[i];
-        const int L = j.inst.L;
-        if (!lattice_ok(L) || L > SG_LDS_MAX_L) return fail(SG_EUNSUPPORTED, "sg_batch_create: job %d has L = %d", i, L);
-        if ((!j.inst.J && !j.inst.jenc) || !j.thr || !j.spins || !j.energy)
-            return fail(SG_EINVAL, "sg_batch_create: job %d has a NULL array", i);
-        if (j.args.n_rep < 1 || j.args.n_sweeps < 1 || j.args.K < 1 || j.args.K > SG_K_MAX || j.args.sweep0 < 0 ||
-            static_cast<int64_t>(j.args.sweep0) + j.args.n_sweeps > (1 << 30))
-            return fail(SG_EINVAL, "sg_batch_create: job %d has invalid arguments", i);
-        if (static_cast<uint64_t>(j.args.rep0) + static_cast<uint64_t>(j.args.n_rep) > 0xFFFFFFFFull)
-            return fail(SG_ERANGE, "sg_batch_create: job %d replica words overflow", i);
-        if ((reinterpret_cast<uintptr_t>(j.spins) & 3u) != 0)
-            return fail(SG_EINVAL, "sg_batch_create: job %d spins not 4-byte aligned", i);
-        by_L[L].push_back(i);
+        const int rc = sa_check_job(jobs[i], i);
+        if (rc != SG_OK) return rc;
+        by_L[jobs[i].inst.L].push_back(i);
     }
     std::unique_ptr<sg_batch> b(new sg_batch());
     b->use_graph = (flags & SG_BATCH_GRAPH) != 0;
@@ -157,29 +100,20 @@ int sg_batch_create(const sg_sa_job *jobs, int32_t n_jobs, int32_t flags, sg_bat
         return fail(SG_EDEVICE, "sg_batch_create: event");
     for (auto &kv : by_L) {
         const int L = kv.first;
-        const int rpw = replicas_per_group(L);
+        int nv = 0;
+        const SaVariant *vs = sa_variants(L, &nv);
+        if (!vs) return fail(SG_EUNSUPPORTED, "sg_batch_create: L = %d", L);
         sg_batch::Bucket bk;
         bk.L = L;
+        bk.variant = sa_selected(L);
+        bk.v = &vs[bk.variant];
+        const int rpw = bk.v->rpw;
         std::vector<SaJob> hj;
         std::vector<Group> hg;
         for (int idx : kv.second) {
             const sg_sa_job &j = jobs[idx];
-            SaJob s{};
-            s.J = j.inst.J;
-            s.jenc = j.inst.jenc;
-            s.thr = j.thr;
-            s.spins = j.spins;
-            s.energy = j.energy;
-            s.emin = j.emin;
-            s.chain = j.inst.chain;
-            s.rep0 = j.args.rep0;
-            s.n_rep = j.args.n_rep;
-            s.n_sweeps = j.args.n_sweeps;
-            s.sweep0 = j.args.sweep0;
-            s.K = j.args.K;
-            s.init_random = j.args.init_random ? 1 : 0;
-            s.k0 = static_cast<uint32_t>(j.args.seed);
-            s.k1 = static_cast<uint32_t>(j.args.seed >> 32);
+            SaJob s;
+            sa_fill_job(s, j);
             if (j.emin) bk.track = true;
             const int g_count = (s.n_rep + rpw - 1) / rpw;
             for (int g = 0; g < g_count; ++g) hg.push_back(Group{static_cast<int32_t>(hj.size()), g});

@@ -26,8 +26,9 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
         const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
-        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        // three-input xor in one gfx950 bitop3 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
         c1 = static_cast<uint32_t>(p1);
         c3 = static_cast<uint32_t>(p0);
         c0 = n0;
@@ -70,16 +71,31 @@ struct Geo {
 // bytewise as E = J + 8 and F = 8 - J (both in [4, 12]).  With n the
 // neighbour-spin dword (0x00/0xFF bytes), bfi(n, F, E) selects 8 + J s_nbr
 // per byte; six directions sum to V = 48 + h per byte without carries.
+// gfx950 v_bitop3_b32: bit i of the result is imm[(a_i << 2) | (b_i << 1) | c_i];
+// 0xE4 is "c ? a : b".  Written as the builtin so that the compiler keeps it
+// one instruction instead of splitting it into and/andn feeding an add.
 __device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b)
 {
-    return (mask & a) | (~mask & b);
+    return __builtin_amdgcn_bitop3_b32(a, b, mask, 0xE4);
 }
 
-// Kb = 48 + k per byte, k = -s h (the flip costs dE = 2k): 96 - V where the
-// own spin is +1 and V where it is -1.
+// Kb = 32 + k per byte, k = -s h (the flip costs dE = 2k): 80 - V where the
+// own spin is +1 and V - 16 where it is -1.  Every byte stays in [8, 56],
+// below 64, so (Kb >> (8b - 2)) & 0x3FF is exactly 4 x byte b: a table
+// address in one bitfield extract.
+constexpr uint32_t kKbBias = 32;
+
 __device__ __forceinline__ uint32_t field_to_kb(uint32_t own, uint32_t V)
 {
-    return bfi(own, V, 0x60606060u - V);
+    return bfi(own, V - 0x10101010u, 0x50505050u - V);
+}
+
+// byte address (4 x Kb byte b) of the threshold entry of site b
+template <int B>
+__device__ __forceinline__ uint32_t kb_addr(uint32_t kb)
+{
+    if (B == 0) return (kb << 2) & 0x3FCu;
+    return __builtin_amdgcn_ubfe(kb, 8 * B - 2, 10);
 }
 
 // byte sum of a dword

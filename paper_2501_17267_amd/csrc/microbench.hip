@@ -43,9 +43,29 @@ __global__ __launch_bounds__(256) void k_probe(uint32_t *out, int iters, uint32_
     out[blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
+// plain streaming copy of n 16-byte words (the reference for scaling the
+// HBM byte counters)
+__global__ __launch_bounds__(256) void k_copy(const uint4 *src, uint4 *dst, int64_t n)
+{
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        dst[i] = src[i];
+}
+
 }  // namespace sg
 
 using namespace sg;
+
+extern "C" int sg_microbench_copy(const void *src, void *dst, int64_t bytes, void *stream)
+{
+    if (!src || !dst || bytes < 16 || (bytes % 16) != 0) return fail(SG_EINVAL, "sg_microbench_copy: bad arguments");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_copy, dim3(256 * 8), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), bytes / 16);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(SG_EDEVICE, "sg_microbench_copy: %s", hipGetErrorString(err));
+    return SG_OK;
+}
 
 extern "C" int sg_microbench_valu(int32_t op, int32_t blocks, int32_t iters, uint32_t *out, void *stream)
 {

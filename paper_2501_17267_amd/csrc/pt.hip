@@ -30,7 +30,7 @@ struct PtJob {
     int32_t pad;
 };
 
-constexpr int kPtThr = 74;  // table entries per ladder slot (Kb clamped to 73)
+constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
 
 template <int L>
 struct PtCfg {
@@ -72,10 +72,7 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     for (int w = tid; w < T * G::SPIN_DW; w += NT) s_spin[w] = 0u;
     for (int w = tid; w < T * kPtThr; w += NT) {
         const int slot = w / kPtThr, e = w - slot * kPtThr;
-        uint32_t v = 0u;
-        if (e <= 48) v = 0xFFFFFFFFu;
-        else if (e - 49 < job.K) v = job.thr[slot * job.K + (e - 49)];
-        s_thr[w] = v;
+        s_thr[w] = thr_entry(job.thr + slot * job.K, job.K, e);
     }
     if (tid < T) {
         s_E[tid] = 0;
@@ -115,7 +112,7 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
             for (int u = tid; u < T * G::NC; u += NT) {
                 const int wk = u / G::NC;
                 const int col = u - wk * G::NC;
-                const int32_t dE = Col::template metropolis<true, true>(
+                const int32_t dE = Col::template metropolis<true>(
                     s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, col,
                     2u * t + static_cast<uint32_t>(c), static_cast<uint32_t>(wk), chain, k0, k1);
                 if (dE != 0) atomicAdd(&s_E[wk], dE);

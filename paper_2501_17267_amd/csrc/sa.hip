@@ -1,83 +1,102 @@
-// sa.hip -- simulated annealing kernel (App. D: Metropolis sweeps over a beta
-// schedule, one read = the final configuration) and its C-ABI entry point.
+// sa.hip -- simulated annealing kernels (App. D: Metropolis sweeps over a
+// beta schedule, one read = the final configuration), their launch-shape
+// variants, the sa_anneal entry point and the variant autotuner.
 //
 // A work group anneals RPW replicas of one instance with the whole lattice
 // resident in LDS: the encoded couplings once per group, RPW spin blocks,
 // and the current threshold row double-buffered.  All NW*64 lanes sweep
 // colour 0 units, barrier, colour 1 units, barrier.
 #include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <vector>
 
-#include "common.hpp"
-#include "sa_kernel.hpp"
+#include "variants.hpp"
 
 namespace sg {
 
 template <int L, int RPW, int NW, bool JF, bool TRACK>
-__global__ __launch_bounds__(NW * 64) void k_sa(SaJob job, uint32_t k0, uint32_t k1)
+__global__ __launch_bounds__(NW * 64) void k_sa(const SaJob *jobs, const Group *groups, SaJob inline_job)
 {
-    sa_group<L, RPW, NW, JF, TRACK>(job, static_cast<int>(blockIdx.x), k0, k1);
-}
-
-template <int L, int RPW, int NW, bool JF>
-static int launch_sa(const SaJob &job, uint32_t k0, uint32_t k1, hipStream_t stream)
-{
-    const int groups = (job.n_rep + RPW - 1) / RPW;
-    (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
-    if (job.emin)
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, true>), dim3(groups), dim3(NW * 64), 0, stream, job, k0, k1);
-    else
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, false>), dim3(groups), dim3(NW * 64), 0, stream, job, k0, k1);
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return fail(SG_EDEVICE, "sa_anneal: launch failed: %s", hipGetErrorString(err));
-    return SG_OK;
-}
-
-int dispatch_sa(int L, const SaJob &job, uint32_t k0, uint32_t k1, hipStream_t stream)
-{
-    switch (L) {
-#define SG_SA_CASE(LL)                                                                  \
-    case LL:                                                                            \
-        return launch_sa<LL, SaCfg<LL>::RPW, SaCfg<LL>::NW, SaCfg<LL>::JF>(job, k0, k1, \
-                                                                           stream);
-        SG_SA_CASE(4)
-        SG_SA_CASE(6)
-        SG_SA_CASE(8)
-        SG_SA_CASE(10)
-        SG_SA_CASE(12)
-        SG_SA_CASE(14)
-        SG_SA_CASE(16)
-        SG_SA_CASE(18)
-        SG_SA_CASE(20)
-        SG_SA_CASE(22)
-        SG_SA_CASE(24)
-#undef SG_SA_CASE
-    default:
-        return fail(SG_EUNSUPPORTED, "sa_anneal: L = %d needs the streaming kernel", L);
+    if (jobs == nullptr) {
+        sa_group<L, RPW, NW, JF, TRACK>(inline_job, static_cast<int>(blockIdx.x), inline_job.k0, inline_job.k1);
+    } else {
+        const Group g = groups[blockIdx.x];
+        const SaJob job = jobs[g.job];
+        sa_group<L, RPW, NW, JF, TRACK>(job, g.group, job.k0, job.k1);
     }
 }
 
-}  // namespace sg
-
-using namespace sg;
-
-extern "C" int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
-                         int8_t *spins, int32_t *energy, int32_t *emin, void *stream)
+template <int L, int RPW, int NW, bool JF>
+static int launch_variant(const SaJob *jobs, const Group *groups, const SaJob &inline_job, int n_groups, bool track,
+                          hipStream_t stream)
 {
-    if (!inst || !args) return fail(SG_EINVAL, "sa_anneal: NULL instance or args");
-    if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "sa_anneal: L = %d must be even in [4, %d]", inst->L, SG_MAX_L);
-    if (!inst->J && !inst->jenc) return fail(SG_EINVAL, "sa_anneal: instance has no couplings");
-    if (!thr || !spins || !energy) return fail(SG_EINVAL, "sa_anneal: NULL thr, spins or energy");
-    if (args->n_rep < 1) return fail(SG_EINVAL, "sa_anneal: n_rep = %d", args->n_rep);
-    if (args->n_sweeps < 1) return fail(SG_EINVAL, "sa_anneal: n_sweeps = %d", args->n_sweeps);
-    if (args->sweep0 < 0 || static_cast<int64_t>(args->sweep0) + args->n_sweeps > (1 << 30))
-        return fail(SG_ERANGE, "sa_anneal: sweeps must stay below 2^30");
-    if (args->K < 1 || args->K > SG_K_MAX) return fail(SG_EINVAL, "sa_anneal: K = %d", args->K);
-    if (static_cast<uint64_t>(args->rep0) + static_cast<uint64_t>(args->n_rep) > 0xFFFFFFFFull)
-        return fail(SG_ERANGE, "sa_anneal: replica counter words overflow");
-    if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0)
-        return fail(SG_EINVAL, "sa_anneal: spins must be 4-byte aligned");
-    if (inst->L > SG_LDS_MAX_L) return fail(SG_EUNSUPPORTED, "sa_anneal: L = %d above the LDS-resident range", inst->L);
-    SaJob job{};
+    (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
+    if (track)
+        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, true>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
+                           inline_job);
+    else
+        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, false>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
+                           inline_job);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(SG_EDEVICE, "annealing kernel launch failed: %s", hipGetErrorString(err));
+    return SG_OK;
+}
+
+template <int L, bool JF>
+constexpr size_t lds_of(int rpw)
+{
+    using G = Geo<L>;
+    return 4 * (2 * kThrEntries + 3 * rpw + (JF ? G::JDW_EF : G::JDW_E) + rpw * G::SPIN_DW);
+}
+
+#define SG_V(L, RPW, NW, JF) {L, RPW, NW, JF, lds_of<L, JF>(RPW), &launch_variant<L, RPW, NW, JF>}
+
+// First entry of each size is its default.  RPW * L^2/2 column units per
+// colour are spread over NW*64 lanes (exactly where the sizes allow).
+static const SaVariant kV4[] = {SG_V(4, 16, 2, true), SG_V(4, 32, 4, true), SG_V(4, 64, 4, true)};
+static const SaVariant kV6[] = {SG_V(6, 32, 3, true), SG_V(6, 32, 9, true), SG_V(6, 64, 9, true)};
+static const SaVariant kV8[] = {SG_V(8, 16, 4, true), SG_V(8, 32, 8, true), SG_V(8, 16, 8, true)};
+static const SaVariant kV10[] = {SG_V(10, 32, 5, true), SG_V(10, 64, 10, true), SG_V(10, 32, 5, false)};
+static const SaVariant kV12[] = {SG_V(12, 16, 9, true), SG_V(12, 16, 6, true), SG_V(12, 32, 9, true),
+                                 SG_V(12, 32, 12, true)};
+static const SaVariant kV14[] = {SG_V(14, 32, 7, false), SG_V(14, 16, 7, true)};
+static const SaVariant kV16[] = {SG_V(16, 16, 16, true), SG_V(16, 16, 8, true), SG_V(16, 8, 8, false),
+                                 SG_V(16, 8, 16, true)};
+static const SaVariant kV18[] = {SG_V(18, 8, 7, false), SG_V(18, 8, 11, false)};
+static const SaVariant kV20[] = {SG_V(20, 8, 5, false), SG_V(20, 4, 5, false)};
+static const SaVariant kV22[] = {SG_V(22, 4, 8, false), SG_V(22, 4, 16, false)};
+static const SaVariant kV24[] = {SG_V(24, 4, 9, false), SG_V(24, 4, 6, false)};
+#undef SG_V
+
+const SaVariant *sa_variants(int L, int *n)
+{
+#define SG_CASE(LL)                                      \
+    case LL:                                             \
+        *n = static_cast<int>(sizeof(kV##LL) / sizeof(kV##LL[0])); \
+        return kV##LL;
+    switch (L) {
+        SG_CASE(4) SG_CASE(6) SG_CASE(8) SG_CASE(10) SG_CASE(12) SG_CASE(14) SG_CASE(16) SG_CASE(18)
+        SG_CASE(20) SG_CASE(22) SG_CASE(24)
+    default:
+        *n = 0;
+        return nullptr;
+    }
+#undef SG_CASE
+}
+
+static std::atomic<int> g_selected[SG_LDS_MAX_L + 1];
+
+int sa_selected(int L)
+{
+    if (L < 0 || L > SG_LDS_MAX_L) return 0;
+    return g_selected[L].load();
+}
+
+static void fill_job(SaJob &job, const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr, int8_t *spins,
+                     int32_t *energy, int32_t *emin)
+{
+    std::memset(&job, 0, sizeof job);
     job.J = inst->J;
     job.jenc = inst->jenc;
     job.thr = thr;
@@ -91,7 +110,111 @@ extern "C" int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const 
     job.sweep0 = args->sweep0;
     job.K = args->K;
     job.init_random = args->init_random ? 1 : 0;
-    clear_error();
-    return dispatch_sa(inst->L, job, static_cast<uint32_t>(args->seed),
-                       static_cast<uint32_t>(args->seed >> 32), static_cast<hipStream_t>(stream));
+    job.k0 = static_cast<uint32_t>(args->seed);
+    job.k1 = static_cast<uint32_t>(args->seed >> 32);
 }
+
+static int check_sa_args(const char *who, const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
+                         const int8_t *spins, const int32_t *energy)
+{
+    if (!inst || !args) return fail(SG_EINVAL, "%s: NULL instance or args", who);
+    if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "%s: L = %d must be even in [4, %d]", who, inst->L, SG_MAX_L);
+    if (!inst->J && !inst->jenc) return fail(SG_EINVAL, "%s: instance has no couplings", who);
+    if (!thr || !spins || !energy) return fail(SG_EINVAL, "%s: NULL thr, spins or energy", who);
+    if (args->n_rep < 1) return fail(SG_EINVAL, "%s: n_rep = %d", who, args->n_rep);
+    if (args->n_sweeps < 1) return fail(SG_EINVAL, "%s: n_sweeps = %d", who, args->n_sweeps);
+    if (args->sweep0 < 0 || static_cast<int64_t>(args->sweep0) + args->n_sweeps > (1 << 30))
+        return fail(SG_ERANGE, "%s: sweeps must stay below 2^30", who);
+    if (args->K < 1 || args->K > SG_K_MAX) return fail(SG_EINVAL, "%s: K = %d", who, args->K);
+    if (static_cast<uint64_t>(args->rep0) + static_cast<uint64_t>(args->n_rep) > 0xFFFFFFFFull)
+        return fail(SG_ERANGE, "%s: replica counter words overflow", who);
+    if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0) return fail(SG_EINVAL, "%s: spins must be 4-byte aligned", who);
+    if (inst->L > SG_LDS_MAX_L)
+        return fail(SG_EUNSUPPORTED, "%s: L = %d above the LDS-resident range", who, inst->L);
+    return SG_OK;
+}
+
+int sa_check_job(const sg_sa_job &j, int index)
+{
+    char who[64];
+    std::snprintf(who, sizeof who, "sg_batch_create: job %d", index);
+    return check_sa_args(who, &j.inst, &j.args, j.thr, j.spins, j.energy);
+}
+
+void sa_fill_job(SaJob &job, const sg_sa_job &j)
+{
+    fill_job(job, &j.inst, &j.args, j.thr, j.spins, j.energy, j.emin);
+}
+
+static int run_variant(const SaVariant &v, const SaJob &job, hipStream_t st)
+{
+    const int groups = (job.n_rep + v.rpw - 1) / v.rpw;
+    return v.launch(nullptr, nullptr, job, groups, job.emin != nullptr, st);
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr, int8_t *spins, int32_t *energy,
+              int32_t *emin, void *stream)
+{
+    const int rc = check_sa_args("sa_anneal", inst, args, thr, spins, energy);
+    if (rc != SG_OK) return rc;
+    int n = 0;
+    const SaVariant *vs = sa_variants(inst->L, &n);
+    if (!vs) return fail(SG_EUNSUPPORTED, "sa_anneal: L = %d", inst->L);
+    SaJob job;
+    fill_job(job, inst, args, thr, spins, energy, emin);
+    clear_error();
+    return run_variant(vs[sa_selected(inst->L)], job, static_cast<hipStream_t>(stream));
+}
+
+int sg_sa_variants(int32_t L, int32_t max, sg_sa_variant *out)
+{
+    int n = 0;
+    const SaVariant *vs = sa_variants(L, &n);
+    if (!vs) return fail(SG_EUNSUPPORTED, "sg_sa_variants: L = %d has no LDS-resident variants", L);
+    for (int i = 0; i < n && i < max && out; ++i) {
+        out[i].L = vs[i].L;
+        out[i].replicas_per_group = vs[i].rpw;
+        out[i].waves_per_group = vs[i].nw;
+        out[i].both_encodings = vs[i].jf;
+        out[i].lds_bytes = static_cast<int64_t>(vs[i].lds_bytes);
+    }
+    return n;
+}
+
+int sg_sa_select_variant(int32_t L, int32_t variant)
+{
+    int n = 0;
+    if (!sa_variants(L, &n)) return fail(SG_EUNSUPPORTED, "sg_sa_select_variant: L = %d", L);
+    if (variant < 0 || variant >= n) return fail(SG_EINVAL, "sg_sa_select_variant: variant %d of %d", variant, n);
+    g_selected[L].store(variant);
+    return SG_OK;
+}
+
+int sg_sa_selected_variant(int32_t L)
+{
+    int n = 0;
+    if (!sa_variants(L, &n)) return fail(SG_EUNSUPPORTED, "sg_sa_selected_variant: L = %d", L);
+    return sa_selected(L);
+}
+
+int sg_sa_anneal_variant(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr, int8_t *spins,
+                         int32_t *energy, int32_t *emin, int32_t variant, void *stream)
+{
+    const int rc = check_sa_args("sg_sa_anneal_variant", inst, args, thr, spins, energy);
+    if (rc != SG_OK) return rc;
+    int n = 0;
+    const SaVariant *vs = sa_variants(inst->L, &n);
+    if (variant < 0 || variant >= n) return fail(SG_EINVAL, "sg_sa_anneal_variant: variant %d of %d", variant, n);
+    SaJob job;
+    fill_job(job, inst, args, thr, spins, energy, emin);
+    clear_error();
+    return run_variant(vs[variant], job, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

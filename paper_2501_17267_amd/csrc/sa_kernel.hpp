@@ -25,24 +25,11 @@ struct SaJob {
     uint32_t k0, k1;        // Philox key (batched launches)
 };
 
-// Launch shape per lattice size: RPW replicas per group, NW waves, JF =
-// keep both coupling encodings (E, F) in LDS.  Chosen so that
-// RPW * L^2/2 column units spread evenly over NW*64 lanes and the group's
-// LDS (couplings + RPW spin blocks) leaves room for a second group where
-// possible.
-template <int L>
-struct SaCfg;
-template <> struct SaCfg<4> { static constexpr int RPW = 16, NW = 2; static constexpr bool JF = true; };
-template <> struct SaCfg<6> { static constexpr int RPW = 32, NW = 3; static constexpr bool JF = true; };
-template <> struct SaCfg<8> { static constexpr int RPW = 16, NW = 4; static constexpr bool JF = true; };
-template <> struct SaCfg<10> { static constexpr int RPW = 32, NW = 5; static constexpr bool JF = true; };
-template <> struct SaCfg<12> { static constexpr int RPW = 16, NW = 6; static constexpr bool JF = true; };
-template <> struct SaCfg<14> { static constexpr int RPW = 32, NW = 7; static constexpr bool JF = false; };
-template <> struct SaCfg<16> { static constexpr int RPW = 16, NW = 8; static constexpr bool JF = true; };
-template <> struct SaCfg<18> { static constexpr int RPW = 8, NW = 7; static constexpr bool JF = false; };
-template <> struct SaCfg<20> { static constexpr int RPW = 8, NW = 5; static constexpr bool JF = false; };
-template <> struct SaCfg<22> { static constexpr int RPW = 4, NW = 8; static constexpr bool JF = false; };
-template <> struct SaCfg<24> { static constexpr int RPW = 4, NW = 9; static constexpr bool JF = false; };
+// A replica group inside a job (batched launches: one work group each).
+struct Group {
+    int32_t job;    // index into the job table
+    int32_t group;  // replica group inside the job
+};
 
 template <int L, int RPW, int NW, bool JF, bool TRACK>
 __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
@@ -51,11 +38,23 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     using Col = Column<L, JF>;
     constexpr int NT = NW * 64;
     constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
-    __shared__ uint32_t s_spin[RPW * G::SPIN_DW];
-    __shared__ uint32_t s_j[JDW];
-    __shared__ uint32_t s_thr[2][256];
-    __shared__ int32_t s_dE[2][RPW];
-    __shared__ int32_t s_E[RPW];
+    // One LDS block: the two threshold tables first (fixed addresses 0 and
+    // 256 bytes, so table lookups need no base register), then per-replica
+    // energy slots, the encoded couplings and the replicas' spins.
+    constexpr int OFF_THR = 0;
+    constexpr int OFF_DE = 2 * kThrEntries;
+    constexpr int OFF_E = OFF_DE + 2 * RPW;
+    constexpr int OFF_J = OFF_E + RPW;
+    constexpr int OFF_SPIN = OFF_J + JDW;
+    constexpr int TOTAL = OFF_SPIN + RPW * G::SPIN_DW;
+    __shared__ uint32_t lds[TOTAL];
+    uint32_t *s_thr0 = lds + OFF_THR;
+    uint32_t *s_thr1 = lds + OFF_THR + kThrEntries;
+    int32_t *s_dE0 = reinterpret_cast<int32_t *>(lds + OFF_DE);
+    int32_t *s_dE1 = s_dE0 + RPW;
+    int32_t *s_E = reinterpret_cast<int32_t *>(lds + OFF_E);
+    uint32_t *s_j = lds + OFF_J;
+    uint32_t *s_spin = lds + OFF_SPIN;
 
     const int tid = static_cast<int>(threadIdx.x);
     const int r_first = group * RPW;
@@ -64,16 +63,13 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
 
     // ---- set-up ---------------------------------------------------------
     for (int w = tid; w < RPW * G::SPIN_DW; w += NT) s_spin[w] = 0u;
-    for (int w = tid; w < 2 * 256; w += NT) {
-        const int e = w & 255;
-        uint32_t v = 0u;
-        if (e <= 48) v = 0xFFFFFFFFu;
-        else if (e - 49 < job.K) v = job.thr[e - 49];
-        s_thr[w >> 8][e] = v;
+    for (int w = tid; w < 2 * kThrEntries; w += NT) {
+        const int e = w % kThrEntries;
+        s_thr0[w] = thr_entry(job.thr, job.K, e);
     }
     if (tid < RPW) {
-        s_dE[0][tid] = 0;
-        s_dE[1][tid] = 0;
+        s_dE0[tid] = 0;
+        s_dE1[tid] = 0;
         s_E[tid] = 0;
     }
     load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
@@ -106,39 +102,47 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     int32_t best = 0x7FFFFFFF;
 
     // ---- sweeps ---------------------------------------------------------
-    for (int si = 0; si < job.n_sweeps; ++si) {
-        const int buf = si & 1;
+    // Two threshold tables at fixed LDS addresses: even sweeps read s_thr0,
+    // odd sweeps s_thr1 (the loop is unrolled by two so that each table's
+    // address is a compile-time constant); the row of sweep si+1 is written
+    // into the other table while sweep si runs.
+    auto sweep = [&](int si, const uint32_t *thr_now, uint32_t *thr_next) {
         const uint32_t s_abs = static_cast<uint32_t>(job.sweep0 + si);
         if (si + 1 < job.n_sweeps && tid < job.K)
-            s_thr[buf ^ 1][49 + tid] = job.thr[static_cast<int64_t>(si + 1) * job.K + tid];
+            thr_next[kKbBias + 1 + tid] = job.thr[static_cast<int64_t>(si + 1) * job.K + tid];
         for (int c = 0; c < 2; ++c) {
             for (int u = tid; u < nact * G::NC; u += NT) {
                 const int rl = u / G::NC;
                 const int col = u - rl * G::NC;
                 const uint32_t rep_word = job.rep0 + static_cast<uint32_t>(r_first + rl);
-                const int32_t dE = Col::template metropolis<TRACK>(s_spin + rl * G::SPIN_DW, s_j, s_thr[buf], c, col,
-                                                   2u * s_abs + static_cast<uint32_t>(c), rep_word,
-                                                   job.chain, k0, k1);
-                if (TRACK && dE != 0) atomicAdd(&s_dE[buf][rl], dE);
+                const int32_t dE = Col::template metropolis<TRACK>(
+                    s_spin + rl * G::SPIN_DW, s_j, thr_now, c, col, 2u * s_abs + static_cast<uint32_t>(c),
+                    rep_word, job.chain, k0, k1);
+                if (TRACK && dE != 0) atomicAdd(&((si & 1) ? s_dE1 : s_dE0)[rl], dE);
             }
             __syncthreads();
         }
         if (track && tid < nact) {
-            s_E[tid] += s_dE[buf][tid];
-            s_dE[buf][tid] = 0;
+            int32_t *acc = (si & 1) ? s_dE1 : s_dE0;
+            s_E[tid] += acc[tid];
+            acc[tid] = 0;
             best = min(best, s_E[tid]);
         }
+    };
+    for (int si = 0; si < job.n_sweeps; si += 2) {
+        sweep(si, s_thr0, s_thr1);
+        if (si + 1 < job.n_sweeps) sweep(si + 1, s_thr1, s_thr0);
     }
 
     // ---- final energy and write-back -----------------------------------
-    if (tid < RPW) s_dE[0][tid] = 0;
+    if (tid < RPW) s_dE0[tid] = 0;
     __syncthreads();
     for (int u = tid; u < nact * G::NC; u += NT) {
         const int rl = u / G::NC;
         const int col = u - rl * G::NC;
         uint32_t own[G::C], kb[G::C];
         Col::fields(s_spin + rl * G::SPIN_DW, s_j, 0, col, own, kb);
-        atomicAdd(&s_dE[0][rl], Col::column_energy(kb));
+        atomicAdd(&s_dE0[rl], Col::column_energy(kb));
     }
     {
         const uint8_t *sb = reinterpret_cast<const uint8_t *>(s_spin);
@@ -152,7 +156,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     }
     __syncthreads();
     if (tid < nact) {
-        job.energy[r_first + tid] = s_dE[0][tid];
+        job.energy[r_first + tid] = s_dE0[tid];
         if (track && job.emin) job.emin[r_first + tid] = best;
     }
 }

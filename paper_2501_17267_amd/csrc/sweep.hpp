@@ -92,26 +92,25 @@ struct Column {
         }
     }
 
-    // sum over the valid sites of the column of s_i h_i = 48 - Kb
+    // sum over the valid sites of the column of s_i h_i = 32 - Kb
     __device__ static int32_t column_energy(const uint32_t (&kb)[C])
     {
         int32_t e = 0;
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             const int nvalid = (G::TAIL != 0 && m == C - 1) ? G::TAIL : 4;
-            e += 48 * nvalid - static_cast<int32_t>(byte_sum(kb[m] & valid(m)));
+            e += static_cast<int32_t>(kKbBias) * nvalid - static_cast<int32_t>(byte_sum(kb[m] & valid(m)));
         }
         return e;
     }
 
     // One Metropolis pass over the column: proposals at every valid site,
     // random words from Philox call (col*C + m, c1, rep_word, chain).
-    // thr: LDS table indexed by Kb: entries 0..48 (k <= 0) are never read
-    // for acceptance, entries 49..48+K hold the thresholds of k = 1..K and
-    // higher entries are zero.  With CLAMP the table has 74 entries and the
-    // index is min(Kb, 73); otherwise it has 256.  Returns the energy change
-    // of the column when TRACK, else 0.
-    template <bool TRACK, bool CLAMP = false>
+    // thr: LDS table of 32-bit thresholds indexed by Kb = 32 + k.  Entries
+    // 33..32+K hold the thresholds of k = 1..K, entries up to 63 beyond K
+    // are zero (never accept); k <= 0 always flips without reading the
+    // table.  Returns the energy change of the column when TRACK, else 0.
+    template <bool TRACK>
     __device__ static int32_t metropolis(uint32_t *rep, const uint32_t *jl, const uint32_t *thr, int c,
                                          int col, uint32_t c1, uint32_t rep_word, uint32_t chain,
                                          uint32_t k0, uint32_t k1)
@@ -119,19 +118,24 @@ struct Column {
         uint32_t own[C], kb[C];
         fields(rep, jl, c, col, own, kb);
         int32_t dE = 0;
+        const char *tb = reinterpret_cast<const char *>(thr);
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             const Rand4 u = philox10(static_cast<uint32_t>(col * C + m), c1, rep_word, chain, k0, k1);
+            uint32_t addr[4];
+            addr[0] = kb_addr<0>(kb[m]);
+            addr[1] = kb_addr<1>(kb[m]);
+            addr[2] = kb_addr<2>(kb[m]);
+            addr[3] = kb_addr<3>(kb[m]);
             uint32_t flip = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (G::TAIL != 0 && m == C - 1 && b >= G::TAIL) continue;
-                const uint32_t kbb = (kb[m] >> (8 * b)) & 0xFFu;
-                const uint32_t t = thr[CLAMP ? min(kbb, 73u) : kbb];
-                // downhill (k <= 0) always; uphill iff u < thr[k]
-                const bool acc = (kbb <= 48u) | (u.w[b] < t);
+                const uint32_t t = *reinterpret_cast<const uint32_t *>(tb + addr[b]);
+                // downhill (k <= 0, i.e. 4 Kb <= 128) always; uphill iff u < thr[k]
+                const bool acc = (addr[b] <= 4u * kKbBias) | (u.w[b] < t);
                 flip |= acc ? (0xFFu << (8 * b)) : 0u;
-                if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(kbb) - 48) : 0;
+                if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(addr[b] >> 2) - static_cast<int32_t>(kKbBias)) : 0;
             }
             own[m] ^= flip;
         }
@@ -145,6 +149,17 @@ struct Column {
 // ---------------------------------------------------------------------------
 // Work-group set-up helpers (natural site order <-> column layout).
 // ---------------------------------------------------------------------------
+
+// entries of an LDS threshold table indexed by Kb = 32 + k
+constexpr int kThrEntries = 64;
+
+// entry e of the table built from one row thr[0..K-1] (k = e - 32)
+__device__ __forceinline__ uint32_t thr_entry(const uint32_t *row, int K, int e)
+{
+    const int k = e - static_cast<int>(kKbBias);
+    if (k <= 0) return 0xFFFFFFFFu;
+    return (k <= K) ? row[k - 1] : 0u;
+}
 
 // byte offset of natural site i inside one replica's column layout
 template <int L>
