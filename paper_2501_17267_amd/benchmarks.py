@@ -133,6 +133,65 @@ def pt(a, sg, wl, torch):
             "eps_best_mean": float(eps.mean()), "eps_best_min": float(eps.min())}
 
 
+def _make_instances(sg, specs, threads=16):
+    """Host-generate instances in parallel (the generator releases the GIL)."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda s: sg.make_instance(s.L, s.cls, s.seed), specs))
+
+
+def uneven(a, sg, wl, torch):
+    """4096 instances of mixed L and sweep budget: one graph-replayed batch
+    against per-instance sa_anneal calls (timed on a stratified subset)."""
+    jobs_spec = wl.uneven()
+    seed = wl.uneven_seed()
+    t0 = time.perf_counter()
+    host = _make_instances(sg, [j.inst for j in jobs_spec])
+    budgets = sorted({j.n_sweeps for j in jobs_spec})
+    thr = {S: sg.to_device_u32(sg.make_thresholds(sg.make_schedule(0, 0.1, 3.0, S))) for S in budgets}
+    insts = [sg.Instance(j.inst.L, h[0], h[2], j.inst.chain) for j, h in zip(jobs_spec, host)]
+    t_host = time.perf_counter() - t0
+    tuning = {}
+    if not getattr(a, "no_autotune", False):
+        for L in sorted({j.inst.L for j in jobs_spec}):
+            res = sg.autotune(L, n_rep=8192, n_sweeps=16, repeats=2)
+            tuning[L] = res["selected"]
+    jobs = [sg.SAJob(inst, thr[j.n_sweeps], j.n_rep, seed) for inst, j in zip(insts, jobs_spec)]
+    batch = sg.Batch(jobs, graph=True)
+    info = batch.info()
+    stream = torch.cuda.current_stream()
+    ms = _time(torch, lambda: batch.launch(stream), a.steps, a.warmup, stream)
+    attempts = info["attempts"]
+    # plain per-instance launches on a stratified subset (every 32nd job)
+    sub = list(range(0, len(jobs_spec), 32))
+    outs = {k: (torch.empty_like(jobs[k].spins), torch.empty_like(jobs[k].energy), None) for k in sub}
+
+    def plain_fn():
+        for k in sub:
+            sg.sa_anneal(insts[k], thr[jobs_spec[k].n_sweeps], jobs_spec[k].n_rep, seed, out=outs[k])
+    pms = _time(torch, plain_fn, 1, 1, stream)
+    sub_att = sum(jobs_spec[k].n_rep * jobs_spec[k].n_sweeps * jobs_spec[k].inst.L ** 3 for k in sub)
+    identical = all(torch.equal(outs[k][0], jobs[k].spins) and torch.equal(outs[k][1], jobs[k].energy)
+                    for k in sub)
+    eps_by_L = {}
+    for inst, job in zip(insts, jobs):
+        e = sg.epsilon(job.energy, inst.E_gs)
+        eps_by_L.setdefault(inst.L, []).append(e)
+    eps_stats = {L: {"mean": float(torch.cat(v).mean()), "frac_le_1pct": float((torch.cat(v) <= 0.01).double().mean())}
+                 for L, v in sorted(eps_by_L.items())}
+    batch.close()
+    return {"metric": "spin-flip attempts/s (uneven batch: 4096 instances, L in {6..20}, 64 replicas, "
+                      "128..1024 sweeps)",
+            "value": attempts / (ms * 1e-3), "unit": "spin-flip attempts/s", "ms_per_step": ms,
+            "attempts_per_step": attempts, "kernels": info["kernels"], "groups": info["groups"],
+            "plain_subset": {"instances": len(sub), "attempts": sub_att, "ms": pms,
+                             "attempts_per_s": sub_att / (pms * 1e-3)},
+            "batched_over_plain": (attempts / (ms * 1e-3)) / (sub_att / (pms * 1e-3)),
+            "bit_identical_batch_vs_plain": identical, "eps_by_L": eps_stats,
+            "launch_shapes": tuning, "host_setup_s": t_host}
+
+
 def run(name, a, sg, wl, torch):
-    fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt}[name]
+    fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
+          "uneven": uneven}[name]
     return fn(a, sg, wl, torch)
