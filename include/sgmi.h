@@ -68,8 +68,10 @@ extern "C" {
 
 /* An instance: the couplings of Eq. 1 plus its planted ground-state energy.
  * jenc: optional device buffer of sg_jenc_bytes(L) bytes filled by
- * sg_encode_instance; required for L > SG_LDS_MAX_L, used to speed up the
- * set-up of smaller ones when present. */
+ * sg_encode_instance; required for L > SG_LDS_MAX_L (whose couplings are
+ * streamed from it during the sweeps), used to speed up the set-up of
+ * smaller ones when present.  sa_anneal supports every even L <= 32 and
+ * L = 64. */
 typedef struct sg_instance {
     int32_t L;
     int32_t reserved;
@@ -95,7 +97,15 @@ typedef struct sg_sa_args {
     int32_t K;           /* row length of thr, 1..SG_K_MAX */
     int32_t init_random; /* 1: draw initial spins from the init stream; 0: use spins[] */
     uint64_t seed;       /* Philox key */
+    void *workspace;     /* device scratch of sg_sa_workspace_bytes(L, n_rep) bytes (16-byte
+                            aligned) when that is nonzero (L > 32), else ignored */
+    int64_t workspace_bytes;
 } sg_sa_args;
+
+/* Device scratch an sa_anneal call of lattice size L with n_rep replicas
+ * needs (the column-layout spin blocks when a lattice does not fit in LDS):
+ * 0 for L <= 32. */
+size_t sg_sa_workspace_bytes(int32_t L, int32_t n_rep);
 
 /* thr:    device uint32 [n_sweeps][K] (from sg_make_thresholds)
  * spins:  device int8 [n_rep][N], input when init_random == 0, output always
@@ -155,7 +165,10 @@ typedef struct sg_sa_variant {
     int32_t L;
     int32_t replicas_per_group;
     int32_t waves_per_group;
-    int32_t both_encodings;   /* 1: E and F coupling encodings in LDS; 0: E only */
+    int32_t both_encodings;   /* 1: E and F coupling encodings; 0: E only */
+    int32_t couplings_in_hbm; /* 1: couplings streamed from the encoded buffer */
+    int32_t spins_in_hbm;     /* 1: spins in the workspace instead of LDS */
+    int32_t reserved;
     int64_t lds_bytes;        /* LDS per work group */
 } sg_sa_variant;
 

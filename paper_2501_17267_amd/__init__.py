@@ -43,7 +43,8 @@ class sg_sa_args(ctypes.Structure):
     _fields_ = [("n_rep", ctypes.c_int32), ("rep0", ctypes.c_uint32),
                 ("n_sweeps", ctypes.c_int32), ("sweep0", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("init_random", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class sg_sa_job(ctypes.Structure):
@@ -54,7 +55,8 @@ class sg_sa_job(ctypes.Structure):
 class sg_sa_variant(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("replicas_per_group", ctypes.c_int32),
                 ("waves_per_group", ctypes.c_int32), ("both_encodings", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int64)]
+                ("couplings_in_hbm", ctypes.c_int32), ("spins_in_hbm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lds_bytes", ctypes.c_int64)]
 
 
 class sg_sa_tune_result(ctypes.Structure):
@@ -103,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.sg_exchange_table_width.argtypes = [vp, c.c_int32]
     L.sg_exchange_table_width.restype = c.c_int32
     L.sg_make_instance.argtypes = [c.c_int32, c.c_int32, c.c_uint64, vp, vp, vp]
+    L.sg_sa_workspace_bytes.restype = c.c_size_t
+    L.sg_sa_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
     L.sg_jenc_bytes.restype = c.c_size_t
     L.sg_jenc_bytes.argtypes = [c.c_int32]
     L.sg_encode_instance.argtypes = [c.POINTER(sg_instance), vp, vp]
@@ -257,6 +261,22 @@ def check_instance(inst: Instance, stream=None) -> int:
     return int(st.item())
 
 
+def _workspace(L: int, n_rep: int, device):
+    """Device scratch for lattices that do not fit in LDS (L > 32), else None."""
+    import torch
+    nbytes = sa_workspace_bytes(L, n_rep)
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes // 4, dtype=torch.int32, device=device)
+
+
+def _with_workspace(args: "sg_sa_args", ws) -> "sg_sa_args":
+    if ws is not None:
+        args.workspace = ws.data_ptr()
+        args.workspace_bytes = ws.numel() * 4
+    return args
+
+
 def sa_anneal(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0: int = 0,
               spins=None, want_emin: bool = False, stream=None, out=None):
     """Anneal n_rep replicas with the threshold rows thr (torch uint32-as-int32
@@ -277,6 +297,8 @@ def sa_anneal(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0:
             sp.copy_(spins)
     args = sg_sa_args(n_rep=n_rep, rep0=rep0, n_sweeps=S, sweep0=sweep0, K=K,
                       init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    ws = _workspace(inst.L, n_rep, dev)
+    _with_workspace(args, ws)
     _check(lib().sa_anneal(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
                            _dptr(sp, "spins"), _dptr(en, "energy"), _dptr(em, "emin"),
                            _stream(stream)), "sa_anneal")
@@ -316,7 +338,12 @@ def sa_variants(L: int) -> list[dict]:
         _check(n, "sg_sa_variants")
     return [{"L": buf[i].L, "replicas_per_group": buf[i].replicas_per_group,
              "waves_per_group": buf[i].waves_per_group, "both_encodings": bool(buf[i].both_encodings),
+             "couplings_in_hbm": bool(buf[i].couplings_in_hbm), "spins_in_hbm": bool(buf[i].spins_in_hbm),
              "lds_bytes": buf[i].lds_bytes} for i in range(n)]
+
+
+def sa_workspace_bytes(L: int, n_rep: int) -> int:
+    return int(lib().sg_sa_workspace_bytes(L, n_rep))
 
 
 def select_variant(L: int, variant: int) -> None:
@@ -343,6 +370,8 @@ def sa_anneal_variant(inst: Instance, thr, n_rep: int, seed: int, variant: int, 
     em = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
     args = sg_sa_args(n_rep=n_rep, rep0=rep0, n_sweeps=S, sweep0=sweep0, K=K,
                       init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    ws = _workspace(inst.L, n_rep, dev)
+    _with_workspace(args, ws)
     _check(lib().sg_sa_anneal_variant(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
                                       _dptr(sp, "spins"), _dptr(en, "energy"), _dptr(em, "emin"),
                                       variant, _stream(stream)), "sg_sa_anneal_variant")
@@ -419,6 +448,7 @@ class SAJob:
         self.spins = torch.empty((n_rep, inst.L ** 3), dtype=torch.int8, device=dev) if spins is None else spins
         self.energy = torch.empty(n_rep, dtype=torch.int32, device=dev)
         self.emin = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
+        self.workspace = _workspace(inst.L, n_rep, dev)
 
     def struct(self) -> sg_sa_job:
         j = sg_sa_job()
@@ -427,6 +457,7 @@ class SAJob:
                             sweep0=self.sweep0, K=int(self.thr.shape[1]),
                             init_random=1 if self.init_random else 0,
                             seed=self.seed & 0xFFFFFFFFFFFFFFFF)
+        _with_workspace(j.args, self.workspace)
         j.thr = self.thr.data_ptr()
         j.spins = self.spins.data_ptr()
         j.energy = self.energy.data_ptr()

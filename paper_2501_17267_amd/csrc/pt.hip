@@ -99,9 +99,7 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     for (int u = tid; u < T * G::NC; u += NT) {
         const int wk = u / G::NC;
         const int col = u - wk * G::NC;
-        uint32_t own[G::C], kb[G::C];
-        Col::fields(s_spin + wk * G::SPIN_DW, s_j, 0, col, own, kb);
-        atomicAdd(&s_E[wk], Col::column_energy(kb));
+        atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * G::SPIN_DW, s_j, col));
     }
     __syncthreads();
 

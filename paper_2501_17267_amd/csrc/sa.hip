@@ -15,42 +15,46 @@
 
 namespace sg {
 
-template <int L, int RPW, int NW, bool JF, bool TRACK>
+template <int L, int RPW, int NW, int JM, bool SL, bool TRACK>
 __global__ __launch_bounds__(NW * 64) void k_sa(const SaJob *jobs, const Group *groups, SaJob inline_job)
 {
     if (jobs == nullptr) {
-        sa_group<L, RPW, NW, JF, TRACK>(inline_job, static_cast<int>(blockIdx.x), inline_job.k0, inline_job.k1);
+        sa_group<L, RPW, NW, JM, SL, TRACK>(inline_job, static_cast<int>(blockIdx.x), inline_job.k0, inline_job.k1);
     } else {
         const Group g = groups[blockIdx.x];
         const SaJob job = jobs[g.job];
-        sa_group<L, RPW, NW, JF, TRACK>(job, g.group, job.k0, job.k1);
+        sa_group<L, RPW, NW, JM, SL, TRACK>(job, g.group, job.k0, job.k1);
     }
 }
 
-template <int L, int RPW, int NW, bool JF>
+template <int L, int RPW, int NW, int JM, bool SL>
 static int launch_variant(const SaJob *jobs, const Group *groups, const SaJob &inline_job, int n_groups, bool track,
                           hipStream_t stream)
 {
     (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
     if (track)
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, true>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
+        hipLaunchKernelGGL((k_sa<L, RPW, NW, JM, SL, true>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
                            inline_job);
     else
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JF, false>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
+        hipLaunchKernelGGL((k_sa<L, RPW, NW, JM, SL, false>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
                            inline_job);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "annealing kernel launch failed: %s", hipGetErrorString(err));
     return SG_OK;
 }
 
-template <int L, bool JF>
+template <int L, int JM, bool SL>
 constexpr size_t lds_of(int rpw)
 {
     using G = Geo<L>;
-    return 4 * (2 * kThrEntries + 3 * rpw + (JF ? G::JDW_EF : G::JDW_E) + rpw * G::SPIN_DW);
+    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsEF ? G::JDW_EF : G::JDW_E);
+    return 4 * (2 * kThrEntries + 3 * rpw + jdw + (SL ? rpw * G::SPIN_DW : 0));
 }
 
-#define SG_V(L, RPW, NW, JF) {L, RPW, NW, JF, lds_of<L, JF>(RPW), &launch_variant<L, RPW, NW, JF>}
+#define SG_VX(L, RPW, NW, JM, SL) \
+    {L, RPW, NW, (JM) == kJLdsE ? 0 : 1, (JM) == kJGlobalEF ? 1 : 0, SL ? 0 : 1, lds_of<L, JM, SL>(RPW), \
+     &launch_variant<L, RPW, NW, JM, SL>}
+#define SG_V(L, RPW, NW, JF) SG_VX(L, RPW, NW, (JF) ? kJLdsEF : kJLdsE, true)
 
 // First entry of each size is its default.  RPW * L^2/2 column units per
 // colour are spread over NW*64 lanes (exactly where the sizes allow).
@@ -67,7 +71,17 @@ static const SaVariant kV18[] = {SG_V(18, 8, 7, false), SG_V(18, 8, 11, false)};
 static const SaVariant kV20[] = {SG_V(20, 8, 5, false), SG_V(20, 4, 5, false)};
 static const SaVariant kV22[] = {SG_V(22, 4, 8, false), SG_V(22, 4, 16, false)};
 static const SaVariant kV24[] = {SG_V(24, 4, 9, false), SG_V(24, 4, 6, false)};
+// couplings streamed from HBM (L2-resident), spins in LDS
+static const SaVariant kV26[] = {SG_VX(26, 2, 11, kJGlobalEF, true), SG_VX(26, 1, 6, kJGlobalEF, true),
+                                 SG_VX(26, 4, 11, kJGlobalEF, true)};
+static const SaVariant kV28[] = {SG_VX(28, 2, 13, kJGlobalEF, true), SG_VX(28, 1, 7, kJGlobalEF, true),
+                                 SG_VX(28, 4, 13, kJGlobalEF, true)};
+static const SaVariant kV30[] = {SG_VX(30, 2, 15, kJGlobalEF, true), SG_VX(30, 1, 8, kJGlobalEF, true)};
+static const SaVariant kV32[] = {SG_VX(32, 2, 16, kJGlobalEF, true), SG_VX(32, 1, 8, kJGlobalEF, true)};
+// couplings and spins both in HBM (a global spin workspace per replica)
+static const SaVariant kV64[] = {SG_VX(64, 1, 16, kJGlobalEF, false), SG_VX(64, 1, 8, kJGlobalEF, false)};
 #undef SG_V
+#undef SG_VX
 
 const SaVariant *sa_variants(int L, int *n)
 {
@@ -77,7 +91,7 @@ const SaVariant *sa_variants(int L, int *n)
         return kV##LL;
     switch (L) {
         SG_CASE(4) SG_CASE(6) SG_CASE(8) SG_CASE(10) SG_CASE(12) SG_CASE(14) SG_CASE(16) SG_CASE(18)
-        SG_CASE(20) SG_CASE(22) SG_CASE(24)
+        SG_CASE(20) SG_CASE(22) SG_CASE(24) SG_CASE(26) SG_CASE(28) SG_CASE(30) SG_CASE(32) SG_CASE(64)
     default:
         *n = 0;
         return nullptr;
@@ -85,11 +99,11 @@ const SaVariant *sa_variants(int L, int *n)
 #undef SG_CASE
 }
 
-static std::atomic<int> g_selected[SG_LDS_MAX_L + 1];
+static std::atomic<int> g_selected[SG_MAX_L + 1];
 
 int sa_selected(int L)
 {
-    if (L < 0 || L > SG_LDS_MAX_L) return 0;
+    if (L < 0 || L > SG_MAX_L) return 0;
     return g_selected[L].load();
 }
 
@@ -112,6 +126,7 @@ static void fill_job(SaJob &job, const sg_instance *inst, const sg_sa_args *args
     job.init_random = args->init_random ? 1 : 0;
     job.k0 = static_cast<uint32_t>(args->seed);
     job.k1 = static_cast<uint32_t>(args->seed >> 32);
+    job.workspace = static_cast<uint32_t *>(args->workspace);
 }
 
 static int check_sa_args(const char *who, const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
@@ -129,8 +144,17 @@ static int check_sa_args(const char *who, const sg_instance *inst, const sg_sa_a
     if (static_cast<uint64_t>(args->rep0) + static_cast<uint64_t>(args->n_rep) > 0xFFFFFFFFull)
         return fail(SG_ERANGE, "%s: replica counter words overflow", who);
     if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0) return fail(SG_EINVAL, "%s: spins must be 4-byte aligned", who);
-    if (inst->L > SG_LDS_MAX_L)
-        return fail(SG_EUNSUPPORTED, "%s: L = %d above the LDS-resident range", who, inst->L);
+    int nv = 0;
+    if (!sa_variants(inst->L, &nv)) return fail(SG_EUNSUPPORTED, "%s: no annealing kernel for L = %d", who, inst->L);
+    if (inst->L > SG_LDS_MAX_L && !inst->jenc)
+        return fail(SG_EINVAL, "%s: L = %d needs the encoded couplings (sg_encode_instance)", who, inst->L);
+    const size_t ws = sg_sa_workspace_bytes(inst->L, args->n_rep);
+    if (ws > 0) {
+        if (!args->workspace || args->workspace_bytes < static_cast<int64_t>(ws))
+            return fail(SG_EINVAL, "%s: L = %d needs a %zu-byte workspace", who, inst->L, ws);
+        if ((reinterpret_cast<uintptr_t>(args->workspace) & 15u) != 0)
+            return fail(SG_EINVAL, "%s: workspace must be 16-byte aligned", who);
+    }
     return SG_OK;
 }
 
@@ -182,9 +206,18 @@ int sg_sa_variants(int32_t L, int32_t max, sg_sa_variant *out)
         out[i].replicas_per_group = vs[i].rpw;
         out[i].waves_per_group = vs[i].nw;
         out[i].both_encodings = vs[i].jf;
+        out[i].couplings_in_hbm = vs[i].jglobal;
+        out[i].spins_in_hbm = vs[i].sglobal;
         out[i].lds_bytes = static_cast<int64_t>(vs[i].lds_bytes);
     }
     return n;
+}
+
+size_t sg_sa_workspace_bytes(int32_t L, int32_t n_rep)
+{
+    if (!lattice_ok(L) || n_rep < 1 || L <= 32) return 0;
+    const size_t H = L / 2, NC = H * L, C = (L + 3) / 4;
+    return static_cast<size_t>(n_rep) * 2 * NC * C * sizeof(uint32_t);
 }
 
 int sg_sa_select_variant(int32_t L, int32_t variant)

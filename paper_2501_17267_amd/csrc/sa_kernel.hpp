@@ -22,7 +22,15 @@ struct SaJob {
     int32_t K;
     int32_t init_random;
     int32_t pad;
-    uint32_t k0, k1;        // Philox key (batched launches)
+    uint32_t k0, k1;        // Philox key
+    uint32_t *workspace;    // global spin blocks when the lattice is not LDS-resident
+};
+
+// Where the couplings live during the anneal.
+enum : int {
+    kJLdsEF = 0,    // LDS, both encodings E = J + 8 and F = 8 - J
+    kJLdsE = 1,     // LDS, E only (F = 16 - E computed per use)
+    kJGlobalEF = 2  // streamed from the encoded HBM buffer (jenc), E and F
 };
 
 // A replica group inside a job (batched launches: one work group each).
@@ -31,33 +39,36 @@ struct Group {
     int32_t group;  // replica group inside the job
 };
 
-template <int L, int RPW, int NW, bool JF, bool TRACK>
+template <int L, int RPW, int NW, int JM, bool SPIN_LDS, bool TRACK>
 __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
+    constexpr bool JF = (JM != kJLdsE);
     using Col = Column<L, JF>;
     constexpr int NT = NW * 64;
-    constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
+    constexpr int JDW = (JM == kJGlobalEF) ? 0 : (JF ? G::JDW_EF : G::JDW_E);
+    constexpr int SDW = SPIN_LDS ? RPW * G::SPIN_DW : 0;
     // One LDS block: the two threshold tables first (fixed addresses 0 and
     // 256 bytes, so table lookups need no base register), then per-replica
-    // energy slots, the encoded couplings and the replicas' spins.
+    // energy slots, the encoded couplings and the replicas' spins (the last
+    // two only when they are LDS-resident).
     constexpr int OFF_THR = 0;
     constexpr int OFF_DE = 2 * kThrEntries;
     constexpr int OFF_E = OFF_DE + 2 * RPW;
     constexpr int OFF_J = OFF_E + RPW;
     constexpr int OFF_SPIN = OFF_J + JDW;
-    constexpr int TOTAL = OFF_SPIN + RPW * G::SPIN_DW;
+    constexpr int TOTAL = OFF_SPIN + SDW;
     __shared__ uint32_t lds[TOTAL];
     uint32_t *s_thr0 = lds + OFF_THR;
     uint32_t *s_thr1 = lds + OFF_THR + kThrEntries;
     int32_t *s_dE0 = reinterpret_cast<int32_t *>(lds + OFF_DE);
     int32_t *s_dE1 = s_dE0 + RPW;
     int32_t *s_E = reinterpret_cast<int32_t *>(lds + OFF_E);
-    uint32_t *s_j = lds + OFF_J;
-    uint32_t *s_spin = lds + OFF_SPIN;
-
     const int tid = static_cast<int>(threadIdx.x);
     const int r_first = group * RPW;
+    const uint32_t *s_j = (JM == kJGlobalEF) ? job.jenc : lds + OFF_J;
+    uint32_t *s_spin = SPIN_LDS ? lds + OFF_SPIN
+                                : job.workspace + static_cast<int64_t>(r_first) * G::SPIN_DW;
     const int nact = min(RPW, job.n_rep - r_first);
     constexpr bool track = TRACK;
 
@@ -72,7 +83,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
         s_dE1[tid] = 0;
         s_E[tid] = 0;
     }
-    load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
+    if (JM != kJGlobalEF) load_couplings<L, JF>(lds + OFF_J, job.J, job.jenc, tid, NT);
     __syncthreads();
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
@@ -93,9 +104,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
         for (int u = tid; u < nact * G::NC; u += NT) {
             const int rl = u / G::NC;
             const int col = u - rl * G::NC;
-            uint32_t own[G::C], kb[G::C];
-            Col::fields(s_spin + rl * G::SPIN_DW, s_j, 0, col, own, kb);
-            atomicAdd(&s_E[rl], Col::column_energy(kb));
+            atomicAdd(&s_E[rl], Col::column_energy_of(s_spin + rl * G::SPIN_DW, s_j, col));
         }
         __syncthreads();
     }
@@ -140,9 +149,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     for (int u = tid; u < nact * G::NC; u += NT) {
         const int rl = u / G::NC;
         const int col = u - rl * G::NC;
-        uint32_t own[G::C], kb[G::C];
-        Col::fields(s_spin + rl * G::SPIN_DW, s_j, 0, col, own, kb);
-        atomicAdd(&s_dE0[rl], Col::column_energy(kb));
+        atomicAdd(&s_dE0[rl], Col::column_energy_of(s_spin + rl * G::SPIN_DW, s_j, col));
     }
     {
         const uint8_t *sb = reinterpret_cast<const uint8_t *>(s_spin);

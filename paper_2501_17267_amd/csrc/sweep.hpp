@@ -92,6 +92,75 @@ struct Column {
         }
     }
 
+    // Kb of dword m of column `col` of colour c, loading only what it needs
+    // (the streaming path for long columns, where holding the whole column
+    // of six neighbour arrays would exceed the register budget).
+    __device__ static uint32_t field_dword(const uint32_t *rep, const uint32_t *jl, int c, int col, int m,
+                                           uint32_t own_m)
+    {
+        const int k = col % H;
+        const int y = col / H;
+        const int kp = (k + 1 == H) ? 0 : k + 1;
+        const int km = (k == 0) ? H - 1 : k - 1;
+        const int yp = (y + 1 == L) ? 0 : y + 1;
+        const int ym = (y == 0) ? L - 1 : y - 1;
+        const uint32_t *other = rep + (c ^ 1) * NC * C;
+        const uint32_t *pS = other + col * C;
+        const uint32_t even_x = ((y + c) & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+        const uint32_t s_m = pS[m];
+        uint32_t zp, zm;
+        if (G::TAIL != 0 && m == C - 1)
+            zp = __builtin_amdgcn_perm(pS[0], s_m, 0x00000401u);
+        else
+            zp = __builtin_amdgcn_alignbyte(pS[m + 1 < C ? m + 1 : 0], s_m, 1);
+        if (G::TAIL != 0 && m == 0)
+            zm = __builtin_amdgcn_perm(s_m, pS[C - 1], 0x06050401u);
+        else
+            zm = __builtin_amdgcn_alignbyte(s_m, pS[m > 0 ? m - 1 : C - 1], 3);
+        const uint32_t nb[6] = {bfi(even_x, s_m, other[(kp + H * y) * C + m]),
+                                bfi(even_x, other[(km + H * y) * C + m], s_m), other[(k + H * yp) * C + m],
+                                other[(k + H * ym) * C + m], zp, zm};
+        const uint32_t *jc = jl + (c * NC + col) * JSTRIDE;
+        uint32_t V = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            uint32_t E, F;
+            if (JF) {
+                E = jc[d * 2 * C + m];
+                F = jc[d * 2 * C + C + m];
+            } else {
+                E = jc[d * C + m];
+                F = 0x10101010u - E;
+            }
+            V += bfi(nb[d], F, E);
+        }
+        return field_to_kb(own_m, V);
+    }
+
+    // columns longer than this are processed dword by dword
+    static constexpr bool kStream = C > 6;
+
+    // sum of s_i h_i over the valid sites of colour-0 column `col`; summed
+    // over all colour-0 columns this is the energy of Eq. 1 (every bond
+    // joins a colour-0 and a colour-1 site)
+    __device__ static int32_t column_energy_of(const uint32_t *rep, const uint32_t *jl, int col)
+    {
+        int32_t e = 0;
+        if constexpr (kStream) {
+            const uint32_t *pO = rep + col * C;
+            for (int m = 0; m < C; ++m) {
+                const uint32_t kbm = field_dword(rep, jl, 0, col, m, pO[m]);
+                const int nvalid = (G::TAIL != 0 && m == C - 1) ? G::TAIL : 4;
+                e += static_cast<int32_t>(kKbBias) * nvalid - static_cast<int32_t>(byte_sum(kbm & valid(m)));
+            }
+        } else {
+            uint32_t own[C], kb[C];
+            fields(rep, jl, 0, col, own, kb);
+            e = column_energy(kb);
+        }
+        return e;
+    }
+
     // sum over the valid sites of the column of s_i h_i = 32 - Kb
     __device__ static int32_t column_energy(const uint32_t (&kb)[C])
     {
@@ -110,11 +179,46 @@ struct Column {
     // 33..32+K hold the thresholds of k = 1..K, entries up to 63 beyond K
     // are zero (never accept); k <= 0 always flips without reading the
     // table.  Returns the energy change of the column when TRACK, else 0.
+    // one dword's four proposals: returns the flip mask, adds to dE
+    template <bool TRACK>
+    __device__ static uint32_t accept_dword(uint32_t kbm, const Rand4 &u, const char *tb, int m, int32_t &dE)
+    {
+        uint32_t addr[4];
+        addr[0] = kb_addr<0>(kbm);
+        addr[1] = kb_addr<1>(kbm);
+        addr[2] = kb_addr<2>(kbm);
+        addr[3] = kb_addr<3>(kbm);
+        uint32_t flip = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (G::TAIL != 0 && m == C - 1 && b >= G::TAIL) continue;
+            const uint32_t t = *reinterpret_cast<const uint32_t *>(tb + addr[b]);
+            const bool acc = (addr[b] <= 4u * kKbBias) | (u.w[b] < t);
+            flip |= acc ? (0xFFu << (8 * b)) : 0u;
+            if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(addr[b] >> 2) - static_cast<int32_t>(kKbBias)) : 0;
+        }
+        return flip;
+    }
+
     template <bool TRACK>
     __device__ static int32_t metropolis(uint32_t *rep, const uint32_t *jl, const uint32_t *thr, int c,
                                          int col, uint32_t c1, uint32_t rep_word, uint32_t chain,
                                          uint32_t k0, uint32_t k1)
     {
+        if constexpr (kStream) {
+            // long columns: dword by dword (same proposals, same order of
+            // effects: this colour's updates never feed this colour's fields)
+            int32_t dE = 0;
+            const char *tb = reinterpret_cast<const char *>(thr);
+            uint32_t *pO = rep + c * NC * C + col * C;
+            for (int m = 0; m < C; ++m) {
+                const uint32_t own_m = pO[m];
+                const uint32_t kbm = field_dword(rep, jl, c, col, m, own_m);
+                const Rand4 u = philox10(static_cast<uint32_t>(col * C + m), c1, rep_word, chain, k0, k1);
+                pO[m] = own_m ^ accept_dword<TRACK>(kbm, u, tb, m, dE);
+            }
+            return dE;
+        }
         uint32_t own[C], kb[C];
         fields(rep, jl, c, col, own, kb);
         int32_t dE = 0;

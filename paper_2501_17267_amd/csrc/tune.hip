@@ -47,10 +47,12 @@ extern "C" int sg_autotune_sa(int32_t L, int32_t n_rep, int32_t n_sweeps, int32_
     rc = sg_make_thresholds(beta.data(), n_sweeps, SG_K_MAX, thr.data());
     if (rc != SG_OK) return rc;
 
-    DevBuf dJ, dThr, dSpins, dE;
+    DevBuf dJ, dThr, dSpins, dE, dJenc, dWs;
     const size_t spin_bytes = static_cast<size_t>(n_rep) * N;
+    const size_t ws_bytes = sg_sa_workspace_bytes(L, n_rep);
     if (!dJ.alloc(J.size()) || !dThr.alloc(thr.size() * 4) || !dSpins.alloc(spin_bytes * nv) ||
-        !dE.alloc(static_cast<size_t>(n_rep) * 4 * nv))
+        !dE.alloc(static_cast<size_t>(n_rep) * 4 * nv) || !dJenc.alloc(sg_jenc_bytes(L)) ||
+        (ws_bytes > 0 && !dWs.alloc(ws_bytes)))
         return fail(SG_ENOMEM, "sg_autotune_sa: device allocation");
     if (hipMemcpy(dJ.p, J.data(), J.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dThr.p, thr.data(), thr.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
@@ -61,12 +63,19 @@ extern "C" int sg_autotune_sa(int32_t L, int32_t n_rep, int32_t n_sweeps, int32_
     inst.J = static_cast<const int8_t *>(dJ.p);
     inst.E_gs = egs;
     inst.chain = 0x5EED;
+    if (L > SG_LDS_MAX_L) {
+        rc = sg_encode_instance(&inst, static_cast<uint32_t *>(dJenc.p), st);
+        if (rc != SG_OK) return rc;
+        inst.jenc = static_cast<const uint32_t *>(dJenc.p);
+    }
     sg_sa_args args{};
     args.n_rep = n_rep;
     args.n_sweeps = n_sweeps;
     args.K = SG_K_MAX;
     args.init_random = 1;
     args.seed = 0x0DDBA11ull;
+    args.workspace = dWs.p;
+    args.workspace_bytes = static_cast<int64_t>(ws_bytes);
 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

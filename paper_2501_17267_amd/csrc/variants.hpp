@@ -18,7 +18,7 @@ using SaLaunchFn = int (*)(const SaJob *jobs, const Group *groups, const SaJob &
                            bool track, hipStream_t stream);
 
 struct SaVariant {
-    int L, rpw, nw, jf;
+    int L, rpw, nw, jf, jglobal, sglobal;
     size_t lds_bytes;
     SaLaunchFn launch;
 };

@@ -22,7 +22,8 @@ def dev_u32(a):
 
 
 def instance(L, seed, chain=0, cls=6, encode=None):
-    """Library-generated instance on the GPU plus the oracle's copy of J."""
+    """Library-generated instance on the GPU plus the oracle's copy of J
+    (encoded couplings are built automatically for L > 24)."""
     J, g, egs = sg.make_instance(L, cls, seed)
     Jo, go, egso = oracle.make_instance(L, cls, seed)
     assert np.array_equal(J, Jo) and egs == egso

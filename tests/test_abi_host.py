@@ -96,8 +96,18 @@ def test_invalid_arguments_are_refused_on_the_host():
     assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, ctypes.c_void_p(0x1001), fake,
                          None, None) == -1
     assert lib.sa_anneal(None, ctypes.byref(args), fake, fake, fake, None, None) == -1
-    inst.L = 32
+    inst.L = 32   # supported, but only with the encoded couplings
+    rc, msg = _bad_call(lib.sa_anneal, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None)
+    assert rc == -1 and "encoded couplings" in msg
+    inst.L = 64   # also needs a workspace
+    inst.jenc = 0x2000
+    rc, msg = _bad_call(lib.sa_anneal, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None)
+    assert rc == -1 and "workspace" in msg
+    assert lib.sg_sa_workspace_bytes(64, 3) == 3 * 2 * 2048 * 16 * 4
+    assert lib.sg_sa_workspace_bytes(32, 3) == 0
+    inst.L = 40   # even and in range, but no kernel is built for it
     assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -7
+    inst.jenc = None
     # PT
     inst.L = 12
     pargs = sg.sg_pt_args(n_runs=2, T=1, n_steps=5, K=24, M=10, init_random=1, seed=3)

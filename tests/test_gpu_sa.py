@@ -43,6 +43,14 @@ def test_sa_bit_exact_every_lattice_size(L):
     _run_and_compare(L, n_rep, 6, 0xA11CE + L, want_emin=True)
 
 
+@pytest.mark.parametrize("L", [26, 28, 30, 32, 64])
+def test_sa_bit_exact_large_lattices(L):
+    # couplings streamed from the encoded HBM buffer; spins in LDS up to
+    # L = 32 and in the global workspace at L = 64
+    n_rep = {26: 5, 28: 3, 30: 3, 32: 3, 64: 2}[L]
+    _run_and_compare(L, n_rep, 3 if L == 64 else 4, 0xB16 + L, want_emin=True)
+
+
 @pytest.mark.parametrize("L", [8, 12])
 def test_sa_bit_exact_without_tracking_and_with_offsets(L):
     _run_and_compare(L, 20, 9, 0xBEE + L, rep0=1000, sweep0=77, want_emin=False)
