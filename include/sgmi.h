@@ -232,6 +232,74 @@ int sg_batch_kernels(const sg_batch *batch, int32_t n, int32_t *L_out, double *a
 /* waits for the plan's work to finish, then frees it */
 int sg_batch_destroy(sg_batch *batch);
 
+/* ---- serving: continuous batching of anneal requests ---------------------------
+ * A request anneals one replica of an instance for n_sweeps sweeps with its
+ * own schedule rows, seed and replica counter word.  A server thread admits
+ * queued requests while the active limit, the memory budget (request state:
+ * spins + energy + workspace) and the pool of large-lattice workspaces
+ * allow, and advances all active requests in chunks of chunk_sweeps: each
+ * lattice size has its own stream, and every time a size's previous chunk
+ * finishes, all its active requests -- including those admitted meanwhile --
+ * run their next chunk together in one kernel.  A request's result depends
+ * only on its own content (instance, schedule, seed, replica word), never on
+ * the mix, the slot or the chunking: it equals one sa_anneal call.
+ * The server allocates its own device memory (job tables, workspace pool)
+ * at creation and when a lattice size first appears; it borrows the request
+ * arrays until the request is done or cancelled. */
+typedef struct sg_server_config {
+    int32_t max_active;      /* requests on the device at once (0: 4096) */
+    int32_t chunk_sweeps;    /* sweeps per request per chunk (0: 64) */
+    int64_t memory_budget;   /* bytes of admitted request state (0: 8 GiB) */
+    int32_t large_slots;     /* preallocated workspaces for lattices above L = 32 */
+    int32_t reserved;
+} sg_server_config;
+
+typedef struct sg_request {
+    sg_instance inst;        /* couplings must stay valid until the request ends */
+    const uint32_t *thr;     /* device [n_sweeps][K] */
+    int32_t n_sweeps;
+    int32_t K;
+    uint64_t seed;           /* Philox key */
+    uint32_t replica;        /* Philox replica counter word */
+    int32_t init_random;     /* 1: init stream; 0: start from spins[] */
+    int8_t *spins;           /* device [N], in/out; final configuration when done */
+    int32_t *energy;         /* device [1]: energy after the latest chunk */
+    double t_arrival;        /* arrival time on the server clock, for latency */
+} sg_request;
+
+#define SG_REQ_QUEUED 0
+#define SG_REQ_ACTIVE 1
+#define SG_REQ_DONE 2
+#define SG_REQ_CANCELLED 3
+#define SG_REQ_FAILED 4
+
+typedef struct sg_request_status {
+    int32_t state;           /* SG_REQ_* */
+    int32_t done_sweeps;
+    double t_arrival, t_admit, t_done;   /* server clock, seconds */
+} sg_request_status;
+
+typedef struct sg_server_stats {
+    int64_t submitted, completed, cancelled, active, queued, launches;
+    double attempts_completed;
+    int64_t memory_in_use;
+} sg_server_stats;
+
+typedef struct sg_server sg_server;
+
+int sg_server_create(const sg_server_config *cfg, sg_server **out);
+double sg_server_now(const sg_server *srv);          /* server clock (steady, seconds) */
+int sg_server_submit(sg_server *srv, const sg_request *req, uint64_t *id_out);
+/* SG_OK with the request's status, SG_ENOTFOUND for an unknown id */
+int sg_server_poll(sg_server *srv, uint64_t id, sg_request_status *out);
+/* queued: dropped at once; active: retired at its next chunk boundary */
+int sg_server_cancel(sg_server *srv, uint64_t id);
+int sg_server_get_stats(sg_server *srv, sg_server_stats *out);
+/* blocks until no request is queued or active (SG_EBUSY on timeout) */
+int sg_server_wait(sg_server *srv, double timeout_s);
+/* cancels what is left, waits for the device, frees the server */
+int sg_server_destroy(sg_server *srv);
+
 /* ---- host helpers (synchronous, no device work) ---------------------------- */
 
 const char *sg_strerror(int code);
