@@ -1,7 +1,7 @@
 // aux.hip -- energy (Eq. 1), optimality gap (Eq. 2), coupling encoding and
 // instance validation kernels with their C-ABI entry points.
 #include "common.hpp"
-#include "device.hpp"
+#include "sweep.hpp"
 
 namespace sg {
 
@@ -49,36 +49,26 @@ __global__ void k_epsilon(const int32_t *E, int64_t n, int64_t E_gs, double *eps
     }
 }
 
-// Encoded couplings: for colour c, column col, direction d, dword m the E
-// (J + 8) and F (8 - J) bytes of the four sites z = 4m .. 4m+3.
-__global__ void k_encode(const int8_t *J, int L, uint32_t *jenc)
+// Encoded couplings (HBM, dword-major so that lanes on adjacent columns
+// read adjacent dwords): for colour c, direction d, half h (E = J + 8,
+// F = 8 - J) and dword m, the dwords of all columns are contiguous.
+template <int L>
+__global__ void k_encode(const int8_t *J, uint32_t *jenc)
 {
-    const int H = L / 2, NC = H * L, C = (L + 3) / 4;
-    const int64_t N = static_cast<int64_t>(L) * L * L;
-    const int64_t total = static_cast<int64_t>(2) * NC * 6 * C;
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    using G = Geo<L>;
+    const int total = 2 * G::NC * 6 * G::C;
+    const int w = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (w >= total) return;
-    const int m = static_cast<int>(w % C);
-    int64_t t = w / C;
-    const int d = static_cast<int>(t % 6);
-    t /= 6;
-    const int col = static_cast<int>(t % NC);
-    const int c = static_cast<int>(t / NC);
-    const int k = col % H, y = col / H;
-    uint32_t e = 0, f = 0;
-    for (int b = 0; b < 4; ++b) {
-        const int z = 4 * m + b;
-        int jv = 0;
-        if (z < L) {
-            const int x = 2 * k + ((y + z + c) & 1);
-            jv = J[d * N + x + static_cast<int64_t>(L) * (y + static_cast<int64_t>(L) * z)];
-        }
-        e |= static_cast<uint32_t>(8 + jv) << (8 * b);
-        f |= static_cast<uint32_t>(8 - jv) << (8 * b);
-    }
-    const int64_t base = (static_cast<int64_t>(c) * NC + col) * 6 + d;
-    jenc[base * 2 * C + m] = e;
-    jenc[base * 2 * C + C + m] = f;
+    const int col = w % G::NC;   // fastest: adjacent threads write adjacent dwords
+    int t = w / G::NC;
+    const int m = t % G::C;
+    t /= G::C;
+    const int d = t % 6;
+    const int c = t / 6;
+    uint32_t e, f;
+    encode_dword<L>(J, c, col, d, m, e, f);
+    jenc[coupling_at<L, 2, kDwordMajor>(c, col, d, 0, m)] = e;
+    jenc[coupling_at<L, 2, kDwordMajor>(c, col, d, 1, m)] = f;
 }
 
 __global__ void k_check(const int8_t *J, int L, int32_t *status)
@@ -159,11 +149,21 @@ int sg_encode_instance(const sg_instance *inst, uint32_t *jenc_out, void *stream
     if (!inst || !inst->J || !jenc_out) return fail(SG_EINVAL, "sg_encode_instance: NULL pointer");
     if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "sg_encode_instance: L = %d", inst->L);
     clear_error();
-    const int64_t total = static_cast<int64_t>(sg_jenc_bytes(inst->L) / sizeof(uint32_t));
+    const int64_t total = static_cast<int64_t>(sg_jenc_bytes(inst->L) / sizeof(uint32_t) / 2);
     const int threads = 256;
+    const dim3 grid(static_cast<unsigned>((total + threads - 1) / threads));
+    hipStream_t st = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_encode, dim3(static_cast<unsigned>((total + threads - 1) / threads)), dim3(threads), 0,
-                       static_cast<hipStream_t>(stream), inst->J, inst->L, jenc_out);
+    switch (inst->L) {
+#define SG_ENC(LL) \
+    case LL: hipLaunchKernelGGL(k_encode<LL>, grid, dim3(threads), 0, st, inst->J, jenc_out); break;
+        SG_ENC(4) SG_ENC(6) SG_ENC(8) SG_ENC(10) SG_ENC(12) SG_ENC(14) SG_ENC(16) SG_ENC(18) SG_ENC(20)
+        SG_ENC(22) SG_ENC(24) SG_ENC(26) SG_ENC(28) SG_ENC(30) SG_ENC(32) SG_ENC(34) SG_ENC(36) SG_ENC(38)
+        SG_ENC(40) SG_ENC(42) SG_ENC(44) SG_ENC(46) SG_ENC(48) SG_ENC(50) SG_ENC(52) SG_ENC(54) SG_ENC(56)
+        SG_ENC(58) SG_ENC(60) SG_ENC(62) SG_ENC(64)
+#undef SG_ENC
+    default: return fail(SG_EINVAL, "sg_encode_instance: L = %d", inst->L);
+    }
     return check_launch("sg_encode_instance");
 }
 

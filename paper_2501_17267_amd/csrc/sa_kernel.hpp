@@ -44,7 +44,10 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
     constexpr bool JF = (JM != kJLdsE);
-    using Col = Column<L, JF>;
+    // LDS arrays column-major, HBM arrays dword-major (coalesced)
+    constexpr int SLAY = SPIN_LDS ? kColMajor : kDwordMajor;
+    constexpr int JLAY = (JM == kJGlobalEF) ? kDwordMajor : kColMajor;
+    using Col = Column<L, JF, SLAY, JLAY>;
     constexpr int NT = NW * 64;
     constexpr int JDW = (JM == kJGlobalEF) ? 0 : (JF ? G::JDW_EF : G::JDW_E);
     constexpr int SDW = SPIN_LDS ? RPW * G::SPIN_DW : 0;
@@ -92,7 +95,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
             const int rl = w / Q;
             const int q = w - rl * Q;
             const int r = r_first + rl;
-            load_spins_one<L>(sb + rl * G::SPIN_DW * 4, q, job.init_random != 0,
+            load_spins_one<L, SLAY>(sb + rl * G::SPIN_DW * 4, q, job.init_random != 0,
                               job.spins + static_cast<int64_t>(r) * G::N,
                               job.rep0 + static_cast<uint32_t>(r), job.chain, k0, k1);
         }
@@ -157,7 +160,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
         for (int w = tid; w < nact * Q; w += NT) {
             const int rl = w / Q;
             const int q = w - rl * Q;
-            store_spins_one<L>(sb + rl * G::SPIN_DW * 4, q,
+            store_spins_one<L, SLAY>(sb + rl * G::SPIN_DW * 4, q,
                                job.spins + static_cast<int64_t>(r_first + rl) * G::N);
         }
     }

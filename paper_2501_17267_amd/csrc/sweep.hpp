@@ -1,25 +1,52 @@
-// sweep.hpp -- the LDS-resident checkerboard Metropolis sweep shared by the
+// sweep.hpp -- the checkerboard Metropolis sweep shared by the
 // simulated-annealing and parallel-tempering kernels.
 //
 // One work unit = one column of one colour of one replica (L sites along z).
-// A lane loads the five neighbouring columns of the other colour, forms the
+// A lane reads the five neighbouring columns of the other colour, forms the
 // packed local fields of its column four sites per dword, draws one
 // Philox4x32-10 call per dword (four proposals), and applies the accepted
 // flips.  Units of the same colour share no bond, so all lanes of a work
 // group update one colour at a time between two barriers.
+//
+// Column arrays (spins of a replica, encoded couplings) come in two layouts:
+//   column-major: dword m of column col of colour c at (c*NC + col)*C + m --
+//                 a lane's column is contiguous (wide LDS reads); used in LDS;
+//   dword-major:  at (c*C + m)*NC + col -- lanes working on adjacent columns
+//                 read adjacent dwords, so HBM loads coalesce; used for
+//                 arrays that stay in HBM.
 #pragma once
 
 #include "device.hpp"
 
 namespace sg {
 
-template <int L, bool JF>
+enum Layout : int { kColMajor = 0, kDwordMajor = 1 };
+
+// index of dword m of column col, colour c, in a replica's spin array
+template <int L, int LAY>
+__device__ __forceinline__ int spin_at(int c, int col, int m)
+{
+    using G = Geo<L>;
+    return LAY == kColMajor ? (c * G::NC + col) * G::C + m : (c * G::C + m) * G::NC + col;
+}
+
+// index of coupling dword m of column col, colour c, direction d, half h
+// (0: E = J + 8, 1: F = 8 - J); HN = 2 when both halves are stored
+template <int L, int HN, int LAY>
+__device__ __forceinline__ int coupling_at(int c, int col, int d, int h, int m)
+{
+    using G = Geo<L>;
+    return LAY == kColMajor ? ((c * G::NC + col) * 6 + d) * HN * G::C + h * G::C + m
+                            : (((c * 6 + d) * HN + h) * G::C + m) * G::NC + col;
+}
+
+template <int L, bool JF, int SLAY = kColMajor, int JLAY = kColMajor>
 struct Column {
     using G = Geo<L>;
     static constexpr int C = G::C;
     static constexpr int H = G::H;
     static constexpr int NC = G::NC;
-    static constexpr int JSTRIDE = JF ? 12 * C : 6 * C;  // dwords of couplings per column
+    static constexpr int HN = JF ? 2 : 1;
 
     // valid-byte mask of dword m (the last dword of a column is half used
     // when L = 2 mod 4)
@@ -28,11 +55,12 @@ struct Column {
         return (G::TAIL != 0 && m == C - 1) ? 0x0000FFFFu : 0xFFFFFFFFu;
     }
 
-    // Kb (= 48 + k per byte) of every dword of column `col` of colour c.
-    // rep: LDS spins of the replica; jl: LDS couplings.  own receives the
-    // column's spin dwords.
-    __device__ static void fields(const uint32_t *rep, const uint32_t *jl, int c, int col,
-                                  uint32_t (&own)[C], uint32_t (&kb)[C])
+    struct Nbr {
+        int self, xp, xm, yp, ym;  // neighbouring columns of the other colour
+        uint32_t even_x;           // bytes whose x is even
+    };
+
+    __device__ static Nbr neighbours(int c, int col)
     {
         const int k = col % H;
         const int y = col / H;
@@ -40,27 +68,48 @@ struct Column {
         const int km = (k == 0) ? H - 1 : k - 1;
         const int yp = (y + 1 == L) ? 0 : y + 1;
         const int ym = (y == 0) ? L - 1 : y - 1;
-        const uint32_t *other = rep + (c ^ 1) * NC * C;
-        const uint32_t *pS = other + col * C;
-        const uint32_t *pXp = other + (kp + H * y) * C;
-        const uint32_t *pXm = other + (km + H * y) * C;
-        const uint32_t *pYp = other + (k + H * yp) * C;
-        const uint32_t *pYm = other + (k + H * ym) * C;
-        const uint32_t *pO = rep + c * NC * C + col * C;
-        // bytes where x is even (p = 0) take the +x neighbour from column k
-        // and the -x neighbour from column k-1
-        const uint32_t even_x = ((y + c) & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+        Nbr n;
+        n.self = col;
+        n.xp = kp + H * y;
+        n.xm = km + H * y;
+        n.yp = k + H * yp;
+        n.ym = k + H * ym;
+        // along a column x alternates between 2k and 2k+1: bytes where x is
+        // even take the +x neighbour from column k and the -x one from k-1
+        n.even_x = ((y + c) & 1) ? 0xFF00FF00u : 0x00FF00FFu;
+        return n;
+    }
+
+    // sum over the six directions of 8 + J s_nbr, per byte
+    __device__ static uint32_t field_sum(const uint32_t *jl, int c, int col, int m, const uint32_t (&nb)[6])
+    {
+        uint32_t V = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const uint32_t E = jl[coupling_at<L, HN, JLAY>(c, col, d, 0, m)];
+            const uint32_t F = JF ? jl[coupling_at<L, HN, JLAY>(c, col, d, 1, m)] : 0x10101010u - E;
+            V += bfi(nb[d], F, E);
+        }
+        return V;
+    }
+
+    // Kb (= 32 + k per byte) of every dword of column `col` of colour c.
+    // rep: spins of the replica; jl: couplings.  own receives the column.
+    __device__ static void fields(const uint32_t *rep, const uint32_t *jl, int c, int col, uint32_t (&own)[C],
+                                  uint32_t (&kb)[C])
+    {
+        const Nbr n = neighbours(c, col);
+        const int oc = c ^ 1;
         uint32_t sv[C], xp[C], xm[C], yv[C], ymv[C];
 #pragma unroll
         for (int m = 0; m < C; ++m) {
-            sv[m] = pS[m];
-            xp[m] = pXp[m];
-            xm[m] = pXm[m];
-            yv[m] = pYp[m];
-            ymv[m] = pYm[m];
-            own[m] = pO[m];
+            sv[m] = rep[spin_at<L, SLAY>(oc, n.self, m)];
+            xp[m] = rep[spin_at<L, SLAY>(oc, n.xp, m)];
+            xm[m] = rep[spin_at<L, SLAY>(oc, n.xm, m)];
+            yv[m] = rep[spin_at<L, SLAY>(oc, n.yp, m)];
+            ymv[m] = rep[spin_at<L, SLAY>(oc, n.ym, m)];
+            own[m] = rep[spin_at<L, SLAY>(c, col, m)];
         }
-        const uint32_t *jc = jl + (c * NC + col) * JSTRIDE;
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             uint32_t zp, zm;
@@ -72,94 +121,37 @@ struct Column {
                 zm = __builtin_amdgcn_perm(sv[0], sv[C - 1], 0x06050401u);
             else
                 zm = __builtin_amdgcn_alignbyte(sv[m], sv[(m + C - 1) % C], 3);
-            const uint32_t nxp = bfi(even_x, sv[m], xp[m]);
-            const uint32_t nxm = bfi(even_x, xm[m], sv[m]);
-            const uint32_t nb[6] = {nxp, nxm, yv[m], ymv[m], zp, zm};
-            uint32_t V = 0;
-#pragma unroll
-            for (int d = 0; d < 6; ++d) {
-                uint32_t E, F;
-                if (JF) {
-                    E = jc[d * 2 * C + m];
-                    F = jc[d * 2 * C + C + m];
-                } else {
-                    E = jc[d * C + m];
-                    F = 0x10101010u - E;
-                }
-                V += bfi(nb[d], F, E);
-            }
-            kb[m] = field_to_kb(own[m], V);
+            const uint32_t nb[6] = {bfi(n.even_x, sv[m], xp[m]), bfi(n.even_x, xm[m], sv[m]), yv[m], ymv[m], zp, zm};
+            kb[m] = field_to_kb(own[m], field_sum(jl, c, col, m, nb));
         }
     }
 
-    // Kb of dword m of column `col` of colour c, loading only what it needs
-    // (the streaming path for long columns, where holding the whole column
-    // of six neighbour arrays would exceed the register budget).
+    // Kb of dword m only, loading just what it needs (the streaming path for
+    // long columns, where six whole neighbour columns would not fit in
+    // registers)
     __device__ static uint32_t field_dword(const uint32_t *rep, const uint32_t *jl, int c, int col, int m,
                                            uint32_t own_m)
     {
-        const int k = col % H;
-        const int y = col / H;
-        const int kp = (k + 1 == H) ? 0 : k + 1;
-        const int km = (k == 0) ? H - 1 : k - 1;
-        const int yp = (y + 1 == L) ? 0 : y + 1;
-        const int ym = (y == 0) ? L - 1 : y - 1;
-        const uint32_t *other = rep + (c ^ 1) * NC * C;
-        const uint32_t *pS = other + col * C;
-        const uint32_t even_x = ((y + c) & 1) ? 0xFF00FF00u : 0x00FF00FFu;
-        const uint32_t s_m = pS[m];
+        const Nbr n = neighbours(c, col);
+        const int oc = c ^ 1;
+        const uint32_t s_m = rep[spin_at<L, SLAY>(oc, n.self, m)];
         uint32_t zp, zm;
         if (G::TAIL != 0 && m == C - 1)
-            zp = __builtin_amdgcn_perm(pS[0], s_m, 0x00000401u);
+            zp = __builtin_amdgcn_perm(rep[spin_at<L, SLAY>(oc, n.self, 0)], s_m, 0x00000401u);
         else
-            zp = __builtin_amdgcn_alignbyte(pS[m + 1 < C ? m + 1 : 0], s_m, 1);
+            zp = __builtin_amdgcn_alignbyte(rep[spin_at<L, SLAY>(oc, n.self, m + 1 < C ? m + 1 : 0)], s_m, 1);
         if (G::TAIL != 0 && m == 0)
-            zm = __builtin_amdgcn_perm(s_m, pS[C - 1], 0x06050401u);
+            zm = __builtin_amdgcn_perm(s_m, rep[spin_at<L, SLAY>(oc, n.self, C - 1)], 0x06050401u);
         else
-            zm = __builtin_amdgcn_alignbyte(s_m, pS[m > 0 ? m - 1 : C - 1], 3);
-        const uint32_t nb[6] = {bfi(even_x, s_m, other[(kp + H * y) * C + m]),
-                                bfi(even_x, other[(km + H * y) * C + m], s_m), other[(k + H * yp) * C + m],
-                                other[(k + H * ym) * C + m], zp, zm};
-        const uint32_t *jc = jl + (c * NC + col) * JSTRIDE;
-        uint32_t V = 0;
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            uint32_t E, F;
-            if (JF) {
-                E = jc[d * 2 * C + m];
-                F = jc[d * 2 * C + C + m];
-            } else {
-                E = jc[d * C + m];
-                F = 0x10101010u - E;
-            }
-            V += bfi(nb[d], F, E);
-        }
-        return field_to_kb(own_m, V);
+            zm = __builtin_amdgcn_alignbyte(s_m, rep[spin_at<L, SLAY>(oc, n.self, m > 0 ? m - 1 : C - 1)], 3);
+        const uint32_t nb[6] = {bfi(n.even_x, s_m, rep[spin_at<L, SLAY>(oc, n.xp, m)]),
+                                bfi(n.even_x, rep[spin_at<L, SLAY>(oc, n.xm, m)], s_m),
+                                rep[spin_at<L, SLAY>(oc, n.yp, m)], rep[spin_at<L, SLAY>(oc, n.ym, m)], zp, zm};
+        return field_to_kb(own_m, field_sum(jl, c, col, m, nb));
     }
 
     // columns longer than this are processed dword by dword
     static constexpr bool kStream = C > 6;
-
-    // sum of s_i h_i over the valid sites of colour-0 column `col`; summed
-    // over all colour-0 columns this is the energy of Eq. 1 (every bond
-    // joins a colour-0 and a colour-1 site)
-    __device__ static int32_t column_energy_of(const uint32_t *rep, const uint32_t *jl, int col)
-    {
-        int32_t e = 0;
-        if constexpr (kStream) {
-            const uint32_t *pO = rep + col * C;
-            for (int m = 0; m < C; ++m) {
-                const uint32_t kbm = field_dword(rep, jl, 0, col, m, pO[m]);
-                const int nvalid = (G::TAIL != 0 && m == C - 1) ? G::TAIL : 4;
-                e += static_cast<int32_t>(kKbBias) * nvalid - static_cast<int32_t>(byte_sum(kbm & valid(m)));
-            }
-        } else {
-            uint32_t own[C], kb[C];
-            fields(rep, jl, 0, col, own, kb);
-            e = column_energy(kb);
-        }
-        return e;
-    }
 
     // sum over the valid sites of the column of s_i h_i = 32 - Kb
     __device__ static int32_t column_energy(const uint32_t (&kb)[C])
@@ -173,13 +165,29 @@ struct Column {
         return e;
     }
 
-    // One Metropolis pass over the column: proposals at every valid site,
-    // random words from Philox call (col*C + m, c1, rep_word, chain).
-    // thr: LDS table of 32-bit thresholds indexed by Kb = 32 + k.  Entries
-    // 33..32+K hold the thresholds of k = 1..K, entries up to 63 beyond K
-    // are zero (never accept); k <= 0 always flips without reading the
-    // table.  Returns the energy change of the column when TRACK, else 0.
-    // one dword's four proposals: returns the flip mask, adds to dE
+    // sum of s_i h_i over the valid sites of colour-0 column `col`; summed
+    // over all colour-0 columns this is the energy of Eq. 1 (every bond
+    // joins a colour-0 and a colour-1 site)
+    __device__ static int32_t column_energy_of(const uint32_t *rep, const uint32_t *jl, int col)
+    {
+        int32_t e = 0;
+        if constexpr (kStream) {
+            for (int m = 0; m < C; ++m) {
+                const uint32_t kbm = field_dword(rep, jl, 0, col, m, rep[spin_at<L, SLAY>(0, col, m)]);
+                const int nvalid = (G::TAIL != 0 && m == C - 1) ? G::TAIL : 4;
+                e += static_cast<int32_t>(kKbBias) * nvalid - static_cast<int32_t>(byte_sum(kbm & valid(m)));
+            }
+        } else {
+            uint32_t own[C], kb[C];
+            fields(rep, jl, 0, col, own, kb);
+            e = column_energy(kb);
+        }
+        return e;
+    }
+
+    // one dword's four proposals: returns the flip mask, adds to dE.
+    // tb: LDS threshold table indexed by Kb = 32 + k (entries 33..32+K hold
+    // the thresholds of k = 1..K, later ones are zero); k <= 0 always flips.
     template <bool TRACK>
     __device__ static uint32_t accept_dword(uint32_t kbm, const Rand4 &u, const char *tb, int m, int32_t &dE)
     {
@@ -193,6 +201,7 @@ struct Column {
         for (int b = 0; b < 4; ++b) {
             if (G::TAIL != 0 && m == C - 1 && b >= G::TAIL) continue;
             const uint32_t t = *reinterpret_cast<const uint32_t *>(tb + addr[b]);
+            // downhill (k <= 0, i.e. 4 Kb <= 128) always; uphill iff u < thr[k]
             const bool acc = (addr[b] <= 4u * kKbBias) | (u.w[b] < t);
             flip |= acc ? (0xFFu << (8 * b)) : 0u;
             if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(addr[b] >> 2) - static_cast<int32_t>(kKbBias)) : 0;
@@ -200,52 +209,36 @@ struct Column {
         return flip;
     }
 
+    // One Metropolis pass over the column: proposals at every valid site,
+    // random words from Philox call (col*C + m, c1, rep_word, chain).
+    // Returns the energy change of the column when TRACK, else 0.
     template <bool TRACK>
-    __device__ static int32_t metropolis(uint32_t *rep, const uint32_t *jl, const uint32_t *thr, int c,
-                                         int col, uint32_t c1, uint32_t rep_word, uint32_t chain,
-                                         uint32_t k0, uint32_t k1)
+    __device__ static int32_t metropolis(uint32_t *rep, const uint32_t *jl, const uint32_t *thr, int c, int col,
+                                         uint32_t c1, uint32_t rep_word, uint32_t chain, uint32_t k0, uint32_t k1)
     {
+        int32_t dE = 0;
+        const char *tb = reinterpret_cast<const char *>(thr);
         if constexpr (kStream) {
-            // long columns: dword by dword (same proposals, same order of
-            // effects: this colour's updates never feed this colour's fields)
-            int32_t dE = 0;
-            const char *tb = reinterpret_cast<const char *>(thr);
-            uint32_t *pO = rep + c * NC * C + col * C;
+            // long columns: dword by dword (this colour's updates never feed
+            // this colour's fields, so the order does not matter)
             for (int m = 0; m < C; ++m) {
-                const uint32_t own_m = pO[m];
+                const int at = spin_at<L, SLAY>(c, col, m);
+                const uint32_t own_m = rep[at];
                 const uint32_t kbm = field_dword(rep, jl, c, col, m, own_m);
                 const Rand4 u = philox10(static_cast<uint32_t>(col * C + m), c1, rep_word, chain, k0, k1);
-                pO[m] = own_m ^ accept_dword<TRACK>(kbm, u, tb, m, dE);
+                rep[at] = own_m ^ accept_dword<TRACK>(kbm, u, tb, m, dE);
             }
             return dE;
         }
         uint32_t own[C], kb[C];
         fields(rep, jl, c, col, own, kb);
-        int32_t dE = 0;
-        const char *tb = reinterpret_cast<const char *>(thr);
 #pragma unroll
         for (int m = 0; m < C; ++m) {
             const Rand4 u = philox10(static_cast<uint32_t>(col * C + m), c1, rep_word, chain, k0, k1);
-            uint32_t addr[4];
-            addr[0] = kb_addr<0>(kb[m]);
-            addr[1] = kb_addr<1>(kb[m]);
-            addr[2] = kb_addr<2>(kb[m]);
-            addr[3] = kb_addr<3>(kb[m]);
-            uint32_t flip = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (G::TAIL != 0 && m == C - 1 && b >= G::TAIL) continue;
-                const uint32_t t = *reinterpret_cast<const uint32_t *>(tb + addr[b]);
-                // downhill (k <= 0, i.e. 4 Kb <= 128) always; uphill iff u < thr[k]
-                const bool acc = (addr[b] <= 4u * kKbBias) | (u.w[b] < t);
-                flip |= acc ? (0xFFu << (8 * b)) : 0u;
-                if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(addr[b] >> 2) - static_cast<int32_t>(kKbBias)) : 0;
-            }
-            own[m] ^= flip;
+            own[m] ^= accept_dword<TRACK>(kb[m], u, tb, m, dE);
         }
-        uint32_t *pO = rep + c * NC * C + col * C;
 #pragma unroll
-        for (int m = 0; m < C; ++m) pO[m] = own[m];
+        for (int m = 0; m < C; ++m) rep[spin_at<L, SLAY>(c, col, m)] = own[m];
         return dE;
     }
 };
@@ -265,8 +258,8 @@ __device__ __forceinline__ uint32_t thr_entry(const uint32_t *row, int K, int e)
     return (k <= K) ? row[k - 1] : 0u;
 }
 
-// byte offset of natural site i inside one replica's column layout
-template <int L>
+// byte offset of natural site i inside one replica's column array
+template <int L, int LAY = kColMajor>
 __device__ __forceinline__ int site_byte(int i)
 {
     using G = Geo<L>;
@@ -275,29 +268,40 @@ __device__ __forceinline__ int site_byte(int i)
     const int z = i / (L * L);
     const int c = (x + y + z) & 1;
     const int col = (x >> 1) + G::H * y;
-    return ((c * G::NC + col) * G::C) * 4 + z;
+    return 4 * spin_at<L, LAY>(c, col, z >> 2) + (z & 3);
 }
 
-// Fill LDS couplings from natural-order J[6][N] (device) or from the
-// pre-encoded buffer (E and F layout) when given.
+// E and F bytes of dword m of column col, colour c, direction d from the
+// natural-order couplings J[6][N] (padding sites: J = 0)
+template <int L>
+__device__ __forceinline__ void encode_dword(const int8_t *J, int c, int col, int d, int m, uint32_t &e, uint32_t &f)
+{
+    using G = Geo<L>;
+    const int k = col % G::H;
+    const int y = col / G::H;
+    e = 0;
+    f = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int z = 4 * m + b;
+        int jv = 0;
+        if (z < L) {
+            const int x = 2 * k + ((y + z + c) & 1);
+            jv = J[d * G::N + x + L * (y + L * z)];
+        }
+        e |= static_cast<uint32_t>(8 + jv) << (8 * b);
+        f |= static_cast<uint32_t>(8 - jv) << (8 * b);
+    }
+}
+
+// Fill the LDS couplings (column-major) from natural-order J[6][N] or from
+// the encoded HBM buffer (dword-major, E and F) when given.
 template <int L, bool JF>
 __device__ void load_couplings(uint32_t *jl, const int8_t *J, const uint32_t *jenc, int tid, int nt)
 {
     using G = Geo<L>;
     constexpr int C = G::C;
-    if (jenc) {
-        if (JF) {
-            for (int w = tid; w < G::JDW_EF; w += nt) jl[w] = jenc[w];
-        } else {
-            // keep the E halves only
-            for (int w = tid; w < G::JDW_E; w += nt) {
-                const int m = w % C;
-                const int cd = w / C;  // (c*NC + col)*6 + d
-                jl[w] = jenc[cd * 2 * C + m];
-            }
-        }
-        return;
-    }
+    constexpr int HN = JF ? 2 : 1;
     for (int w = tid; w < 2 * G::NC * 6 * C; w += nt) {
         const int m = w % C;
         int t = w / C;
@@ -305,35 +309,23 @@ __device__ void load_couplings(uint32_t *jl, const int8_t *J, const uint32_t *je
         t /= 6;
         const int col = t % G::NC;
         const int c = t / G::NC;
-        const int k = col % G::H;
-        const int y = col / G::H;
-        uint32_t e = 0, f = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int z = 4 * m + b;
-            int jv = 0;
-            if (z < L) {
-                const int x = 2 * k + ((y + z + c) & 1);
-                jv = J[d * G::N + x + L * (y + L * z)];
-            }
-            e |= static_cast<uint32_t>(8 + jv) << (8 * b);
-            f |= static_cast<uint32_t>(8 - jv) << (8 * b);
-        }
-        const int base = ((c * G::NC + col) * 6 + d);
-        if (JF) {
-            jl[base * 2 * C + m] = e;
-            jl[base * 2 * C + C + m] = f;
+        uint32_t e, f;
+        if (jenc) {
+            e = jenc[coupling_at<L, 2, kDwordMajor>(c, col, d, 0, m)];
+            f = jenc[coupling_at<L, 2, kDwordMajor>(c, col, d, 1, m)];
         } else {
-            jl[base * C + m] = e;
+            encode_dword<L>(J, c, col, d, m, e, f);
         }
+        jl[coupling_at<L, HN, kColMajor>(c, col, d, 0, m)] = e;
+        if (JF) jl[coupling_at<L, HN, kColMajor>(c, col, d, 1, m)] = f;
     }
 }
 
 // Initial spins of one replica: from the init stream or from natural-order
-// int8 spins.  The replica's LDS block must be zeroed beforehand (padding).
-template <int L>
-__device__ void load_spins_one(uint8_t *repb, int q, bool init_random, const int8_t *src,
-                               uint32_t rep_word, uint32_t chain, uint32_t k0, uint32_t k1)
+// int8 spins.  The replica's array must be zeroed beforehand (padding).
+template <int L, int LAY = kColMajor>
+__device__ void load_spins_one(uint8_t *repb, int q, bool init_random, const int8_t *src, uint32_t rep_word,
+                               uint32_t chain, uint32_t k0, uint32_t k1)
 {
     uint32_t w4[4];
     if (init_random) {
@@ -346,16 +338,16 @@ __device__ void load_spins_one(uint8_t *repb, int q, bool init_random, const int
         for (int b = 0; b < 4; ++b) w4[b] = (((v >> (8 * b)) & 0x80u) != 0) ? 0xFFu : 0u;
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) repb[site_byte<L>(4 * q + b)] = static_cast<uint8_t>(w4[b]);
+    for (int b = 0; b < 4; ++b) repb[site_byte<L, LAY>(4 * q + b)] = static_cast<uint8_t>(w4[b]);
 }
 
-template <int L>
+template <int L, int LAY = kColMajor>
 __device__ __forceinline__ void store_spins_one(const uint8_t *repb, int q, int8_t *dst)
 {
     uint32_t v = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const uint32_t s = repb[site_byte<L>(4 * q + b)] ? 0xFFu : 0x01u;
+        const uint32_t s = repb[site_byte<L, LAY>(4 * q + b)] ? 0xFFu : 0x01u;
         v |= s << (8 * b);
     }
     reinterpret_cast<uint32_t *>(dst)[q] = v;
