@@ -80,10 +80,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "microbench", "copy"])
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "microbench", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: measured seconds")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second")
+    ap.add_argument("--chunk", type=int, default=512, help="serve: most sweeps per chunk")
+    ap.add_argument("--chunk-attempts", type=int, default=1 << 24,
+                    help="serve: target spin-flip attempts per request per chunk")
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="hardware queues for this process (GPU_MAX_HW_QUEUES, <= 32); "
+                         "serve defaults to 16, one per lattice-size stream")
     ap.add_argument("--no-graph-compare", action="store_true",
                     help="skip timing the same schedule replayed as a hipGraph")
     return ap.parse_args()
@@ -158,6 +166,12 @@ def cpu_baseline_sa(w, thr_h, target_s):
 
 def main():
     a = parse()
+    if a.hw_queues is None and a.workload == "serve":
+        a.hw_queues = 16
+    if a.hw_queues:
+        # one stream per lattice size in the server: more hardware queues
+        # let their kernels run side by side (must be set before HIP starts)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, a.hw_queues))
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))

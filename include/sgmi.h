@@ -248,10 +248,13 @@ int sg_batch_destroy(sg_batch *batch);
  * arrays until the request is done or cancelled. */
 typedef struct sg_server_config {
     int32_t max_active;      /* requests on the device at once (0: 4096) */
-    int32_t chunk_sweeps;    /* sweeps per request per chunk (0: 64) */
+    int32_t chunk_sweeps;    /* most sweeps per request per chunk (0: 64) */
     int64_t memory_budget;   /* bytes of admitted request state (0: 8 GiB) */
     int32_t large_slots;     /* preallocated workspaces for lattices above L = 32 */
     int32_t reserved;
+    int64_t chunk_attempts;  /* > 0: a size's chunk is max(1, min(chunk_sweeps,
+                                chunk_attempts / L^3)) sweeps, so chunks of all sizes
+                                take similar time; 0: chunk_sweeps for every size */
 } sg_server_config;
 
 typedef struct sg_request {

@@ -191,7 +191,26 @@ def uneven(a, sg, wl, torch):
             "launch_shapes": tuning, "host_setup_s": t_host}
 
 
+def serve(a, sg, wl, torch):
+    """Poisson stream of anneal requests through the continuous-batching server."""
+    from . import serving
+    import sys
+    dur = float(getattr(a, "duration", 60.0))
+    res = serving.run_poisson(torch, rate=float(getattr(a, "rate", 2000.0)), duration=dur,
+                              warmup=min(10.0, dur / 6), seed=wl.philox_seed("serve") & 0xFFFF,
+                              pool=4, chunk=int(getattr(a, "chunk", 512)),
+                              chunk_attempts=int(getattr(a, "chunk_attempts", 1 << 24)),
+                              log=lambda *m: print("[serve]", *m, file=sys.stderr, flush=True))
+    res["metric"] = ("served spin-flip attempts/s and latency (Poisson 2000 req/s, L even 8..32 "
+                     "+ 5% L=64, sweeps log-uniform 64..4096, one replica per request)")
+    res["value"] = res["attempts_per_s"]
+    import os
+    res["hw_queues"] = os.environ.get("GPU_MAX_HW_QUEUES", "default")
+    res["unit"] = "spin-flip attempts/s"
+    return res
+
+
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven}[name]
+          "uneven": uneven, "serve": serve}[name]
     return fn(a, sg, wl, torch)

@@ -21,7 +21,8 @@ __global__ __launch_bounds__(NW * 64) void k_sa(const SaJob *jobs, const Group *
     if (jobs == nullptr) {
         sa_group<L, RPW, NW, JM, SL, TRACK>(inline_job, static_cast<int>(blockIdx.x), inline_job.k0, inline_job.k1);
     } else {
-        const Group g = groups[blockIdx.x];
+        // groups == NULL: one group per job, job index = block index
+        const Group g = groups ? groups[blockIdx.x] : Group{static_cast<int32_t>(blockIdx.x), 0};
         const SaJob job = jobs[g.job];
         sa_group<L, RPW, NW, JM, SL, TRACK>(job, g.group, job.k0, job.k1);
     }

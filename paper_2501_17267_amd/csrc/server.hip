@@ -54,9 +54,8 @@ struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     SaJob *h_jobs = nullptr;   // pinned staging
-    Group *h_groups = nullptr;
     SaJob *d_jobs = nullptr;
-    Group *d_groups = nullptr;
+    int32_t chunk = 1;         // sweeps per chunk for this size
     bool busy = false;
     std::vector<uint64_t> chunk_ids;
     std::vector<int32_t> chunk_sweeps;
@@ -104,9 +103,7 @@ struct sg_server {
             Lane &ln = *kv.second;
             if (ln.stream) (void)hipStreamSynchronize(ln.stream);
             if (ln.d_jobs) (void)hipFree(ln.d_jobs);
-            if (ln.d_groups) (void)hipFree(ln.d_groups);
             if (ln.h_jobs) (void)hipHostFree(ln.h_jobs);
-            if (ln.h_groups) (void)hipHostFree(ln.h_groups);
             if (ln.done) (void)hipEventDestroy(ln.done);
             if (ln.stream) (void)hipStreamDestroy(ln.stream);
         }
@@ -120,15 +117,20 @@ struct sg_server {
         std::unique_ptr<Lane> ln(new Lane());
         ln->L = L;
         if (pick_variant(L, &ln->v) != SG_OK) return nullptr;
+        // chunks of about chunk_attempts proposals per request (at most
+        // chunk_sweeps sweeps), so that chunks of all sizes take similar time
+        // and no size waits long behind another in a shared hardware queue
+        const int64_t N = static_cast<int64_t>(L) * L * L;
+        ln->chunk = cfg.chunk_sweeps;
+        if (cfg.chunk_attempts > 0)
+            ln->chunk = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(cfg.chunk_sweeps,
+                                                                                   cfg.chunk_attempts / N)));
         const size_t nj = static_cast<size_t>(cfg.max_active);
         if (hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ln->done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void **>(&ln->h_jobs), nj * sizeof(SaJob), hipHostMallocDefault) !=
                 hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&ln->h_groups), nj * sizeof(Group), hipHostMallocDefault) !=
-                hipSuccess ||
-            hipMalloc(&ln->d_jobs, nj * sizeof(SaJob)) != hipSuccess ||
-            hipMalloc(&ln->d_groups, nj * sizeof(Group)) != hipSuccess) {
+            hipMalloc(&ln->d_jobs, nj * sizeof(SaJob)) != hipSuccess) {
             lanes[L] = std::move(ln);  // freed by the destructor
             return nullptr;
         }
@@ -222,7 +224,7 @@ struct sg_server {
                 release(q);
                 continue;
             }
-            const int32_t chunk = std::min(cfg.chunk_sweeps, q.r.n_sweeps - q.done);
+            const int32_t chunk = std::min(ln.chunk, q.r.n_sweeps - q.done);
             SaJob &j = ln.h_jobs[n];
             std::memset(&j, 0, sizeof j);
             j.J = q.r.inst.J;
@@ -240,7 +242,6 @@ struct sg_server {
             j.k0 = static_cast<uint32_t>(q.r.seed);
             j.k1 = static_cast<uint32_t>(q.r.seed >> 32);
             j.workspace = q.ws_slot >= 0 ? static_cast<uint32_t *>(ws_pool[q.ws_slot]) : nullptr;
-            ln.h_groups[n] = Group{n, 0};
             q.in_flight = true;
             ln.chunk_ids.push_back(id);
             ln.chunk_sweeps.push_back(chunk);
@@ -255,12 +256,11 @@ struct sg_server {
 
     int launch(Lane &ln, int n)
     {
-        if (hipMemcpyAsync(ln.d_jobs, ln.h_jobs, n * sizeof(SaJob), hipMemcpyHostToDevice, ln.stream) != hipSuccess ||
-            hipMemcpyAsync(ln.d_groups, ln.h_groups, n * sizeof(Group), hipMemcpyHostToDevice, ln.stream) !=
-                hipSuccess)
+        if (hipMemcpyAsync(ln.d_jobs, ln.h_jobs, n * sizeof(SaJob), hipMemcpyHostToDevice, ln.stream) != hipSuccess)
             return fail(SG_EDEVICE, "sg_server: upload");
         const SaJob none{};
-        const int rc = ln.v->launch(ln.d_jobs, ln.d_groups, none, n, false, ln.stream);
+        // one replica per request: one work group per job, no group table
+        const int rc = ln.v->launch(ln.d_jobs, nullptr, none, n, false, ln.stream);
         if (rc != SG_OK) return rc;
         if (hipEventRecord(ln.done, ln.stream) != hipSuccess) return fail(SG_EDEVICE, "sg_server: event");
         return SG_OK;
@@ -333,6 +333,7 @@ int sg_server_create(const sg_server_config *cfg, sg_server **out)
     if (cfg) s->cfg = *cfg;
     if (s->cfg.max_active <= 0) s->cfg.max_active = 4096;
     if (s->cfg.chunk_sweeps <= 0) s->cfg.chunk_sweeps = 64;
+    if (s->cfg.chunk_attempts < 0) return fail(SG_EINVAL, "sg_server_create: chunk_attempts < 0");
     if (s->cfg.memory_budget <= 0) s->cfg.memory_budget = int64_t(8) << 30;
     if (s->cfg.large_slots < 0) return fail(SG_EINVAL, "sg_server_create: large_slots < 0");
     if (hipGetDevice(&s->device) != hipSuccess) return fail(SG_EDEVICE, "sg_server_create: no device");

@@ -20,7 +20,7 @@ SG_REQ_QUEUED, SG_REQ_ACTIVE, SG_REQ_DONE, SG_REQ_CANCELLED, SG_REQ_FAILED = ran
 class sg_server_config(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("chunk_sweeps", ctypes.c_int32),
                 ("memory_budget", ctypes.c_int64), ("large_slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("chunk_attempts", ctypes.c_int64)]
 
 
 class sg_request(ctypes.Structure):
@@ -69,9 +69,11 @@ def _lib():
 class Server:
     """A running anneal server on the current device."""
 
-    def __init__(self, max_active=4096, chunk_sweeps=64, memory_budget=8 << 30, large_slots=64):
+    def __init__(self, max_active=4096, chunk_sweeps=64, memory_budget=8 << 30, large_slots=64,
+                 chunk_attempts=0):
         cfg = sg_server_config(max_active=max_active, chunk_sweeps=chunk_sweeps,
-                               memory_budget=memory_budget, large_slots=large_slots)
+                               memory_budget=memory_budget, large_slots=large_slots,
+                               chunk_attempts=chunk_attempts)
         h = ctypes.c_void_p()
         _check(_lib().sg_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sg_server_create")
         self.h = h
@@ -156,8 +158,9 @@ def make_stream(rate, duration, seed, p_large=0.05, pool=4, grid=None):
     return {"t": t, "L": L.astype(int), "k": k.astype(int), "S": S.astype(int)}
 
 
-def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool=4, chunk=64,
-                p_large=0.05, plain_sample=64, check_sample=32, log=print, instance_seed=None):
+def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool=4, chunk=512,
+                chunk_attempts=1 << 24, p_large=0.05, plain_sample=64, check_sample=32, log=print,
+                instance_seed=None):
     """Drive a server with a Poisson stream; return latency and throughput."""
     from . import sa_anneal, epsilon
     from . import workloads as wl
@@ -180,7 +183,7 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
     energy = torch.zeros(n, dtype=torch.int32, device="cuda")
     t_setup = time.perf_counter() - t0
     log(f"serve: {n} requests over {total:.0f} s, sizes {sizes}, set-up {t_setup:.1f} s")
-    srv = Server(max_active=8192, chunk_sweeps=chunk, large_slots=256)
+    srv = Server(max_active=8192, chunk_sweeps=chunk, large_slots=256, chunk_attempts=chunk_attempts)
     key = wl.philox_seed("serve")
     ids = []
     base = srv.now() + 0.2
@@ -250,6 +253,7 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
         "plain_sequential_attempts_per_s": plain_rate, "served_over_plain": served_rate / plain_rate,
         "served_equals_alone": ident, "eps_mean": float(eps[meas].mean()),
         "eps_frac_le_1pct": float((eps[meas] <= 0.01).mean()), "by_class": by_class,
-        "chunk_sweeps": chunk, "kernel_launches": stats["launches"], "set_up_s": t_setup,
+        "chunk_sweeps_max": chunk, "chunk_attempts": chunk_attempts,
+        "kernel_launches": stats["launches"], "set_up_s": t_setup,
         "drain_s": float(end - (base + total)),
     }
