@@ -80,7 +80,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "microbench", "copy"])
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "microbench",
+                             "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")

@@ -210,7 +210,16 @@ def serve(a, sg, wl, torch):
     return res
 
 
+def tteps(a, sg, wl, torch):
+    """Time-to-eps at eps = 1% (and 3%, 5%) versus N, plain / batched / served."""
+    from . import tteps as tt
+    import sys
+    res = tt.run(torch, log=lambda *m: print("[tteps]", *m, file=sys.stderr, flush=True))
+    res["metric"] = "TT-eps at eps = 1% (3%, 5%) vs N; plain, batched and served forms"
+    return res
+
+
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve}[name]
+          "uneven": uneven, "serve": serve, "tteps": tteps}[name]
     return fn(a, sg, wl, torch)
