@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--variants", default=None,
+                    help="fixed launch shapes instead of autotuning, e.g. 8=2,12=3,16=3 "
+                         "(to profile exactly the shapes an earlier run selected)")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: measured seconds")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: requests per second")
     ap.add_argument("--chunk", type=int, default=512, help="serve: most sweeps per chunk")
@@ -194,7 +197,12 @@ def main():
         return
 
     tuning = {}
-    if not a.no_autotune:
+    if a.variants:
+        for item in a.variants.split(","):
+            L, v = (int(x) for x in item.split("="))
+            sg.select_variant(L, v)
+            tuning[L] = {"variant": v, **sg.sa_variants(L)[v], "fixed": True}
+    elif not a.no_autotune:
         # launch shapes chosen on the device before the timed region
         for L in sorted({s.L for s in wl.sa_batch().instances}):
             res = sg.autotune(L, n_rep=16384, n_sweeps=32, repeats=2)
