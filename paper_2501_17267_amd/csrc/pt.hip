@@ -34,9 +34,28 @@ constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
 
 template <int L>
 struct PtCfg {
-    static constexpr int NW = (L <= 8) ? 4 : (L <= 12 ? 9 : 16);
     static constexpr bool JF = (L <= 12);
 };
+
+// Waves per work group for T walkers of size L: the T * L^2/2 column units
+// of a colour phase are dealt to NW * 64 lanes in ceil(units / (NW*64))
+// passes.  Pick the NW with the least idle lane-passes (passes * NW), the
+// larger NW on ties (more waves to hide LDS latency).
+constexpr int kPtWaves[] = {4, 8, 12, 16};
+inline int pt_waves(int L, int T)
+{
+    const int units = T * L * L / 2;
+    int best = 4, best_cost = 1 << 30;
+    for (int nw : kPtWaves) {
+        const int passes = (units + nw * 64 - 1) / (nw * 64);
+        const int cost = passes * nw;
+        if (cost < best_cost || (cost == best_cost && nw > best)) {
+            best = nw;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
 
 template <int L, bool JF>
 constexpr size_t pt_lds_bytes(int T)
@@ -163,22 +182,33 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     }
 }
 
-template <int L>
-static int launch_pt(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+template <int L, int NW>
+static int launch_pt_nw(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
     using Cfg = PtCfg<L>;
     const size_t bytes = pt_lds_bytes<L, Cfg::JF>(job.T);
     if (bytes > 160 * 1024)
         return fail(SG_EUNSUPPORTED, "pt_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
-    auto kern = k_pt<L, Cfg::NW, Cfg::JF>;
+    auto kern = k_pt<L, NW, Cfg::JF>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: LDS attribute: %s", hipGetErrorString(err));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(Cfg::NW * 64), bytes, stream, job, k0, k1);
+    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(NW * 64), bytes, stream, job, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: launch failed: %s", hipGetErrorString(err));
     return SG_OK;
+}
+
+template <int L>
+static int launch_pt(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+{
+    switch (pt_waves(L, job.T)) {
+    case 4: return launch_pt_nw<L, 4>(job, n_runs, k0, k1, stream);
+    case 8: return launch_pt_nw<L, 8>(job, n_runs, k0, k1, stream);
+    case 12: return launch_pt_nw<L, 12>(job, n_runs, k0, k1, stream);
+    default: return launch_pt_nw<L, 16>(job, n_runs, k0, k1, stream);
+    }
 }
 
 }  // namespace sg

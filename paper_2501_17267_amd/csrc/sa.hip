@@ -49,7 +49,7 @@ constexpr size_t lds_of(int rpw)
 {
     using G = Geo<L>;
     const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsEF ? G::JDW_EF : G::JDW_E);
-    return 4 * (2 * kThrEntries + 3 * rpw + jdw + (SL ? rpw * G::SPIN_DW : 0));
+    return 4 * (((2 * kThrEntries + 3 * rpw + 3) & ~3) + jdw + (SL ? rpw * G::SPIN_DW : 0));
 }
 
 #define SG_VX(L, RPW, NW, JM, SL) \
@@ -69,7 +69,8 @@ static const SaVariant kV12[] = {SG_V(12, 16, 9, true), SG_V(12, 16, 6, true), S
                                  SG_V(12, 32, 12, true), SG_V(12, 1, 1, true)};
 static const SaVariant kV14[] = {SG_V(14, 32, 7, false), SG_V(14, 16, 7, true), SG_V(14, 1, 2, true)};
 static const SaVariant kV16[] = {SG_V(16, 16, 16, true), SG_V(16, 16, 8, true), SG_V(16, 8, 8, false),
-                                 SG_V(16, 8, 16, true), SG_V(16, 1, 2, true)};
+                                 SG_V(16, 8, 16, true), SG_V(16, 1, 2, true), SG_V(16, 7, 14, true),
+                                 SG_V(16, 6, 12, true)};
 static const SaVariant kV18[] = {SG_V(18, 8, 7, false), SG_V(18, 8, 11, false), SG_V(18, 1, 3, true)};
 static const SaVariant kV20[] = {SG_V(20, 8, 5, false), SG_V(20, 4, 5, false), SG_V(20, 1, 4, true)};
 static const SaVariant kV22[] = {SG_V(22, 4, 8, false), SG_V(22, 4, 16, false), SG_V(22, 1, 4, true)};

@@ -58,7 +58,9 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     constexpr int OFF_THR = 0;
     constexpr int OFF_DE = 2 * kThrEntries;
     constexpr int OFF_E = OFF_DE + 2 * RPW;
-    constexpr int OFF_J = OFF_E + RPW;
+    // couplings and spins start on a 16-byte boundary so that column reads
+    // are single 128-bit LDS accesses whatever RPW is
+    constexpr int OFF_J = (OFF_E + RPW + 3) & ~3;
     constexpr int OFF_SPIN = OFF_J + JDW;
     constexpr int TOTAL = OFF_SPIN + SDW;
     __shared__ uint32_t lds[TOTAL];

@@ -31,13 +31,33 @@ __device__ __forceinline__ int spin_at(int c, int col, int m)
 }
 
 // index of coupling dword m of column col, colour c, direction d, half h
-// (0: E = J + 8, 1: F = 8 - J); HN = 2 when both halves are stored
+// (0: E = J + 8, 1: F = 8 - J); HN = 2 when both halves are stored.
+// In LDS (kColMajor) a lane reads, per direction, the C dwords of its own
+// column, and the lanes of a wave read adjacent columns.  The arrangement
+// is chosen per column length so that those reads are single wide accesses
+// and the wave's addresses spread over all LDS banks:
+//   C = 4:          one plane per (colour, direction, half); columns 16 B
+//                   apart (128-bit reads, consecutive lanes consecutive);
+//   HN*C = 2 or 4:  one plane per (colour, direction) with E and F of a
+//                   column side by side (one 64/128-bit read for both);
+//   otherwise:      all twelve (direction, half) blocks of a column side by
+//                   side; a column stride of 6*HN*C dwords (36, 60, 72 ...)
+//                   already lands successive lanes on distinct banks.
+template <int L, int HN>
+__device__ __forceinline__ constexpr int lds_jmode()
+{
+    return Geo<L>::C == 4 ? 0 : ((HN * Geo<L>::C == 2 || HN * Geo<L>::C == 4) ? 1 : 2);
+}
+
 template <int L, int HN, int LAY>
 __device__ __forceinline__ int coupling_at(int c, int col, int d, int h, int m)
 {
     using G = Geo<L>;
-    return LAY == kColMajor ? ((c * G::NC + col) * 6 + d) * HN * G::C + h * G::C + m
-                            : (((c * 6 + d) * HN + h) * G::C + m) * G::NC + col;
+    if (LAY == kDwordMajor) return (((c * 6 + d) * HN + h) * G::C + m) * G::NC + col;
+    constexpr int mode = lds_jmode<L, HN>();
+    if (mode == 0) return (((c * 6 + d) * HN + h) * G::NC + col) * G::C + m;
+    if (mode == 1) return ((c * 6 + d) * G::NC + col) * HN * G::C + h * G::C + m;
+    return ((c * G::NC + col) * 6 + d) * HN * G::C + h * G::C + m;
 }
 
 template <int L, bool JF, int SLAY = kColMajor, int JLAY = kColMajor>
