@@ -203,9 +203,10 @@ def main():
             sg.select_variant(L, v)
             tuning[L] = {"variant": v, **sg.sa_variants(L)[v], "fixed": True}
     elif not a.no_autotune:
-        # launch shapes chosen on the device before the timed region
+        # launch shapes chosen on the device before the timed region, timed
+        # at the workload's sweep count (per-group set-up weighs as it will)
         for L in sorted({s.L for s in wl.sa_batch().instances}):
-            res = sg.autotune(L, n_rep=16384, n_sweeps=32, repeats=2)
+            res = sg.autotune(L, n_rep=16384, n_sweeps=wl.sa_batch().n_sweeps, repeats=2)
             v = res["selected"]
             tuning[L] = {"variant": v, **sg.sa_variants(L)[v],
                          "candidates_ms": [round(r["ms"], 4) for r in res["results"]]}

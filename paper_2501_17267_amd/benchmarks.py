@@ -154,7 +154,7 @@ def uneven(a, sg, wl, torch):
     tuning = {}
     if not getattr(a, "no_autotune", False):
         for L in sorted({j.inst.L for j in jobs_spec}):
-            res = sg.autotune(L, n_rep=8192, n_sweeps=16, repeats=2)
+            res = sg.autotune(L, n_rep=8192, n_sweeps=256, repeats=2)
             tuning[L] = res["selected"]
     jobs = [sg.SAJob(inst, thr[j.n_sweeps], j.n_rep, seed) for inst, j in zip(insts, jobs_spec)]
     batch = sg.Batch(jobs, graph=True)

@@ -44,6 +44,93 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return out;
 }
 
+// The same function with the counter split into words fixed for a whole
+// anneal (0, 2, 3 and the key) and word 1 (2s + c, the sweep and colour).
+// Following each word through the rounds: round 1's products use words 0
+// and 2 only; round 2's product of word 2 and round 3's product of word 0
+// are again independent of word 1.  philox_pre computes those three products
+// once per call site, philox_hp the word-2 part of round 1 shared by all
+// calls of a lane, and per (word 1, lane) philox_q0 is the one product that
+// all calls of the lane share; philox_finish then needs one product in
+// round 3 and two in each of rounds 4..10 (15 instead of 20).
+// philox_finish(philox_pre(c0, c2, c3), philox_q0(philox_hp(c2), c1)) ==
+// philox10(c0, c1, c2, c3) for the same key.
+struct PhiloxPre {
+    uint32_t x3;   // round-1 output word 3 (low product of word 0)
+    uint32_t y1;   // round-2 output word 1
+    uint32_t hr0;  // round-3 high product of word 0
+    uint32_t lr0;  // round-3 low product of word 0 (= round-3 output word 3)
+};
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint32_t philox_hp(uint32_t c2, uint32_t k0)
+{
+    return static_cast<uint32_t>((static_cast<uint64_t>(c2) * kPhiloxM1) >> 32) ^ k0;
+}
+
+__device__ __forceinline__ PhiloxPre philox_pre(uint32_t c0, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = static_cast<uint64_t>(c0) * kPhiloxM0;
+    const uint64_t p1 = static_cast<uint64_t>(c2) * kPhiloxM1;
+    // round 1 (word 0 of its output needs word 1 and is left to the caller)
+    const uint32_t x1 = static_cast<uint32_t>(p1);
+    const uint32_t x2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
+    const uint32_t x3 = static_cast<uint32_t>(p0);
+    // round 2: the product of word 2 and the output words 0 and 1
+    const uint64_t q1 = static_cast<uint64_t>(x2) * kPhiloxM1;
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(q1 >> 32), x1, k0 + kPhiloxW0, 0x96);
+    // round 3: the product of word 0
+    const uint64_t r0 = static_cast<uint64_t>(y0) * kPhiloxM0;
+    PhiloxPre p;
+    p.x3 = x3;
+    p.y1 = static_cast<uint32_t>(q1);
+    p.hr0 = static_cast<uint32_t>(r0 >> 32);
+    p.lr0 = static_cast<uint32_t>(r0);
+    return p;
+}
+
+// round-2 product of word 0 for word 1 = c1 (shared by the calls of a lane)
+__device__ __forceinline__ uint64_t philox_q0(uint32_t hp, uint32_t c1)
+{
+    return static_cast<uint64_t>(hp ^ c1) * kPhiloxM0;
+}
+
+__device__ __forceinline__ Rand4 philox_finish(const PhiloxPre &p, uint64_t q0, uint32_t k0, uint32_t k1)
+{
+    // round 2, output words 2 and 3
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(q0 >> 32), p.x3, k1 + kPhiloxW1, 0x96);
+    const uint32_t y3 = static_cast<uint32_t>(q0);
+    // round 3
+    const uint64_t r1 = static_cast<uint64_t>(y2) * kPhiloxM1;
+    uint32_t c0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(r1 >> 32), p.y1, k0 + 2u * kPhiloxW0, 0x96);
+    uint32_t c1 = static_cast<uint32_t>(r1);
+    uint32_t c2 = __builtin_amdgcn_bitop3_b32(p.hr0, y3, k1 + 2u * kPhiloxW1, 0x96);
+    uint32_t c3 = p.lr0;
+    k0 += 3u * kPhiloxW0;
+    k1 += 3u * kPhiloxW1;
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        const uint64_t a = static_cast<uint64_t>(c0) * kPhiloxM0;
+        const uint64_t b = static_cast<uint64_t>(c2) * kPhiloxM1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(b >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(a >> 32), c3, k1, 0x96);
+        c1 = static_cast<uint32_t>(b);
+        c3 = static_cast<uint32_t>(a);
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Rand4 out;
+    out.w[0] = c0;
+    out.w[1] = c1;
+    out.w[2] = c2;
+    out.w[3] = c3;
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // Colour-split column layout.  For colour c, the sites with x+y+z = c (mod 2)
 // form L^2/2 columns indexed col = k + (L/2) y (k = floor(x/2)); a column

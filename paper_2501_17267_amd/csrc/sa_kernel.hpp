@@ -120,21 +120,60 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     // odd sweeps s_thr1 (the loop is unrolled by two so that each table's
     // address is a compile-time constant); the row of sweep si+1 is written
     // into the other table while sweep si runs.
+    // Columns held whole in registers: each lane's units (column, replica)
+    // are fixed for the anneal, so their neighbour columns and the
+    // sweep-independent part of their Philox calls are prepared once.
+    // Only where that state (4 words per dword + 8 per unit) fits in about
+    // 40 registers per lane; shapes with more units per lane keep the
+    // per-sweep path.
+    constexpr int UPL = (RPW * G::NC + NT - 1) / NT;
+    constexpr bool kPrep = !Col::kStream && UPL * (4 * G::C + 8) <= 40;
+    typename Col::Unit un[kPrep ? UPL : 1];
+    int rls[kPrep ? UPL : 1];
+    bool act[kPrep ? UPL : 1];
+    if constexpr (kPrep) {
+#pragma unroll
+        for (int i = 0; i < UPL; ++i) {
+            const int u = tid + i * NT;
+            act[i] = u < nact * G::NC;
+            const int ua = act[i] ? u : 0;
+            const int rl = ua / G::NC;
+            const int col = ua - rl * G::NC;
+            rls[i] = rl;
+            un[i] = Col::make_unit(col, job.rep0 + static_cast<uint32_t>(r_first + rl), job.chain, k0, k1);
+        }
+    }
+
     auto sweep = [&](int si, const uint32_t *thr_now, uint32_t *thr_next) {
         const uint32_t s_abs = static_cast<uint32_t>(job.sweep0 + si);
         if (si + 1 < job.n_sweeps && tid < job.K)
             thr_next[kKbBias + 1 + tid] = job.thr[static_cast<int64_t>(si + 1) * job.K + tid];
-        for (int c = 0; c < 2; ++c) {
-            for (int u = tid; u < nact * G::NC; u += NT) {
-                const int rl = u / G::NC;
-                const int col = u - rl * G::NC;
-                const uint32_t rep_word = job.rep0 + static_cast<uint32_t>(r_first + rl);
-                const int32_t dE = Col::template metropolis<TRACK>(
-                    s_spin + rl * G::SPIN_DW, s_j, thr_now, c, col, 2u * s_abs + static_cast<uint32_t>(c),
-                    rep_word, job.chain, k0, k1);
-                if (TRACK && dE != 0) atomicAdd(&((si & 1) ? s_dE1 : s_dE0)[rl], dE);
+        if constexpr (kPrep) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int i = 0; i < UPL; ++i) {
+                    if (!act[i]) continue;
+                    const int32_t dE = Col::template metropolis_unit<TRACK>(
+                        s_spin + rls[i] * G::SPIN_DW, s_j, thr_now, c, un[i], 2u * s_abs + static_cast<uint32_t>(c), k0,
+                        k1);
+                    if (TRACK && dE != 0) atomicAdd(&((si & 1) ? s_dE1 : s_dE0)[rls[i]], dE);
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                for (int u = tid; u < nact * G::NC; u += NT) {
+                    const int rl = u / G::NC;
+                    const int col = u - rl * G::NC;
+                    const uint32_t rep_word = job.rep0 + static_cast<uint32_t>(r_first + rl);
+                    const int32_t dE = Col::template metropolis<TRACK>(
+                        s_spin + rl * G::SPIN_DW, s_j, thr_now, c, col, 2u * s_abs + static_cast<uint32_t>(c),
+                        rep_word, job.chain, k0, k1);
+                    if (TRACK && dE != 0) atomicAdd(&((si & 1) ? s_dE1 : s_dE0)[rl], dE);
+                }
+                __syncthreads();
+            }
         }
         if (track && tid < nact) {
             int32_t *acc = (si & 1) ? s_dE1 : s_dE0;

@@ -118,7 +118,12 @@ struct Column {
     __device__ static void fields(const uint32_t *rep, const uint32_t *jl, int c, int col, uint32_t (&own)[C],
                                   uint32_t (&kb)[C])
     {
-        const Nbr n = neighbours(c, col);
+        fields_n(rep, jl, c, col, neighbours(c, col), own, kb);
+    }
+
+    __device__ static void fields_n(const uint32_t *rep, const uint32_t *jl, int c, int col, const Nbr &n,
+                                    uint32_t (&own)[C], uint32_t (&kb)[C])
+    {
         const int oc = c ^ 1;
         uint32_t sv[C], xp[C], xm[C], yv[C], ymv[C];
 #pragma unroll
@@ -259,6 +264,49 @@ struct Column {
         }
 #pragma unroll
         for (int m = 0; m < C; ++m) rep[spin_at<L, SLAY>(c, col, m)] = own[m];
+        return dE;
+    }
+
+    // A unit whose column and replica stay fixed for a whole anneal: its
+    // neighbour columns and the word-1-independent part of the Philox calls
+    // of its C dwords (counter (col*C + m, ., rep_word, chain)) are computed
+    // once.  Only for columns held whole in registers (not kStream).
+    struct Unit {
+        Nbr n;            // as seen from colour 0; colour 1 flips even_x
+        uint32_t hp;      // philox_hp(rep_word, k0)
+        PhiloxPre pre[C];
+    };
+
+    __device__ static Unit make_unit(int col, uint32_t rep_word, uint32_t chain, uint32_t k0, uint32_t k1)
+    {
+        Unit u;
+        u.n = neighbours(0, col);
+        u.hp = philox_hp(rep_word, k0);
+#pragma unroll
+        for (int m = 0; m < C; ++m) u.pre[m] = philox_pre(static_cast<uint32_t>(col * C + m), rep_word, chain, k0, k1);
+        return u;
+    }
+
+    // metropolis() for a prepared unit; c1 = 2s + c.  Same result.
+    template <bool TRACK>
+    __device__ static int32_t metropolis_unit(uint32_t *rep, const uint32_t *jl, const uint32_t *thr, int c,
+                                              const Unit &un, uint32_t c1, uint32_t k0, uint32_t k1)
+    {
+        static_assert(!kStream, "prepared units hold whole columns");
+        int32_t dE = 0;
+        const char *tb = reinterpret_cast<const char *>(thr);
+        Nbr n = un.n;
+        if (c) n.even_x = ~n.even_x;
+        uint32_t own[C], kb[C];
+        fields_n(rep, jl, c, n.self, n, own, kb);
+        const uint64_t q0 = philox_q0(un.hp, c1);
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+            const Rand4 u = philox_finish(un.pre[m], q0, k0, k1);
+            own[m] ^= accept_dword<TRACK>(kb[m], u, tb, m, dE);
+        }
+#pragma unroll
+        for (int m = 0; m < C; ++m) rep[spin_at<L, SLAY>(c, n.self, m)] = own[m];
         return dE;
     }
 };
