@@ -5,6 +5,8 @@
 // colour-0 pass over all walkers' columns, a colour-1 pass, then the
 // even/odd replica exchange done by one lane per ladder pair, all inside
 // the group, so a run never leaves its compute unit.
+#include <algorithm>
+
 #include "common.hpp"
 #include "sweep.hpp"
 
@@ -27,7 +29,7 @@ struct PtJob {
     int32_t K;
     int32_t M;
     int32_t init_random;
-    int32_t pad;
+    int32_t mx;             // exchange-table entries per ladder pair copied to LDS
 };
 
 constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
@@ -57,15 +59,30 @@ inline int pt_waves(int L, int T)
     return best;
 }
 
+// LDS of one run: T spin blocks, the couplings, T threshold tables, four
+// per-walker words and the first mx entries of each pair's exchange table
 template <int L, bool JF>
-constexpr size_t pt_lds_bytes(int T)
+constexpr size_t pt_lds_bytes(int T, int mx)
 {
     using G = Geo<L>;
     return (static_cast<size_t>(T) * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) +
-            static_cast<size_t>(T) * kPtThr + 4 * static_cast<size_t>(T)) * 4;
+            static_cast<size_t>(T) * kPtThr + 4 * static_cast<size_t>(T) +
+            static_cast<size_t>(T - 1) * static_cast<size_t>(mx)) * 4;
 }
 
-template <int L, int NW, bool JF>
+// Units (walker, column) a lane may hold prepared (neighbours and the
+// sweep-independent Philox products, as in the annealing kernel): the
+// register file gives each lane 512 / ceil(NW/4) registers, about 100 of
+// which the sweep itself needs; a prepared unit takes 4 per dword + 8.
+template <int L, int NW>
+constexpr int pt_umax()
+{
+    constexpr int regs = 512 / ((NW + 3) / 4) - 100;
+    constexpr int per = 4 * Geo<L>::C + 8;
+    return (regs / per) < 4 ? regs / per : 4;
+}
+
+template <int L, int NW, bool JF, bool PREP>
 __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
@@ -81,6 +98,8 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     int32_t *s_pos = s_E + T;
     int32_t *s_who = s_pos + T;
     int32_t *s_sw = s_who + T;
+    uint32_t *s_thrx = reinterpret_cast<uint32_t *>(s_sw + T);
+    const int mx = job.mx;
 
     const int tid = static_cast<int>(threadIdx.x);
     const int run = static_cast<int>(blockIdx.x);
@@ -92,6 +111,10 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     for (int w = tid; w < T * kPtThr; w += NT) {
         const int slot = w / kPtThr, e = w - slot * kPtThr;
         s_thr[w] = thr_entry(job.thr + slot * job.K, job.K, e);
+    }
+    for (int w = tid; w < (T - 1) * mx; w += NT) {
+        const int k = w / mx, e = w - k * mx;
+        s_thrx[w] = job.thrx[static_cast<int64_t>(k) * job.M + e];
     }
     if (tid < T) {
         s_E[tid] = 0;
@@ -122,19 +145,53 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     }
     __syncthreads();
 
+    // prepared units: a lane keeps the same (walker, column) units for the
+    // whole run (the launcher guarantees they number at most UMAX)
+    constexpr int UMAX = PREP ? pt_umax<L, NW>() : 1;
+    typename Col::Unit un[UMAX];
+    int wks[UMAX];
+    bool act[UMAX];
+    if constexpr (PREP) {
+#pragma unroll
+        for (int i = 0; i < UMAX; ++i) {
+            const int u = tid + i * NT;
+            act[i] = u < T * G::NC;
+            const int ua = act[i] ? u : 0;
+            const int wk = ua / G::NC;
+            wks[i] = wk;
+            un[i] = Col::make_unit(ua - wk * G::NC, static_cast<uint32_t>(wk), chain, k0, k1);
+        }
+    }
+
     // ---- steps ------------------------------------------------------------
     for (int ti = 0; ti < job.n_steps; ++ti) {
         const uint32_t t = static_cast<uint32_t>(job.step0 + ti);
-        for (int c = 0; c < 2; ++c) {
-            for (int u = tid; u < T * G::NC; u += NT) {
-                const int wk = u / G::NC;
-                const int col = u - wk * G::NC;
-                const int32_t dE = Col::template metropolis<true>(
-                    s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, col,
-                    2u * t + static_cast<uint32_t>(c), static_cast<uint32_t>(wk), chain, k0, k1);
-                if (dE != 0) atomicAdd(&s_E[wk], dE);
+        if constexpr (PREP) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int i = 0; i < UMAX; ++i) {
+                    if (!act[i]) continue;
+                    const int wk = wks[i];
+                    const int32_t dE = Col::template metropolis_unit<true>(
+                        s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, un[i],
+                        2u * t + static_cast<uint32_t>(c), k0, k1);
+                    if (dE != 0) atomicAdd(&s_E[wk], dE);
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                for (int u = tid; u < T * G::NC; u += NT) {
+                    const int wk = u / G::NC;
+                    const int col = u - wk * G::NC;
+                    const int32_t dE = Col::template metropolis<true>(
+                        s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, col,
+                        2u * t + static_cast<uint32_t>(c), static_cast<uint32_t>(wk), chain, k0, k1);
+                    if (dE != 0) atomicAdd(&s_E[wk], dE);
+                }
+                __syncthreads();
+            }
         }
         // exchange of ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ...
         const int k = tid;
@@ -145,7 +202,10 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
             if (!acc) {
                 const int32_t m = D / 2;
                 const Rand4 u = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFFu, chain, k0, k1);
-                acc = (m <= job.M) && (u.w[0] < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
+                if (m <= mx)
+                    acc = u.w[0] < s_thrx[k * mx + (m - 1)];
+                else
+                    acc = (m <= job.M) && (u.w[0] < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
             }
             if (acc) {
                 s_who[k] = b;
@@ -183,13 +243,21 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
 }
 
 template <int L, int NW>
-static int launch_pt_nw(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+static int launch_pt_nw(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
     using Cfg = PtCfg<L>;
-    const size_t bytes = pt_lds_bytes<L, Cfg::JF>(job.T);
-    if (bytes > 160 * 1024)
-        return fail(SG_EUNSUPPORTED, "pt_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
-    auto kern = k_pt<L, NW, Cfg::JF>;
+    constexpr size_t kLds = 160 * 1024;
+    const size_t base = pt_lds_bytes<L, Cfg::JF>(job.T, 0);
+    if (base > kLds)
+        return fail(SG_EUNSUPPORTED, "pt_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, base);
+    // the exchange-table prefix held in LDS: up to 128 entries per pair,
+    // as many as the LDS left over allows (later entries are read from HBM)
+    job.mx = static_cast<int32_t>(std::min<size_t>({static_cast<size_t>(job.M), 128,
+                                                   (kLds - base) / (4 * static_cast<size_t>(job.T - 1))}));
+    const size_t bytes = pt_lds_bytes<L, Cfg::JF>(job.T, job.mx);
+    const int units = job.T * Geo<L>::NC;
+    const int upl = (units + NW * 64 - 1) / (NW * 64);
+    auto kern = (upl <= pt_umax<L, NW>()) ? k_pt<L, NW, Cfg::JF, true> : k_pt<L, NW, Cfg::JF, false>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: LDS attribute: %s", hipGetErrorString(err));
