@@ -114,6 +114,25 @@ size_t sg_sa_workspace_bytes(int32_t L, int32_t n_rep);
 int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
               int8_t *spins, int32_t *energy, int32_t *emin, void *stream);
 
+/* Few replicas of a large lattice (L = 26..32 and 64), spread over the
+ * whole device.  The method is that of sa_anneal (App. D sweeps, same
+ * counters, same result), but each colour phase of each sweep is one
+ * launch with one lane per column dword of every replica, instead of one
+ * work group per replica group; it cuts the time of one anneal when
+ * n_rep is small.  Requires args->workspace of at least
+ * n_rep * L^2 * ceil(L/4) * 4 bytes (16-byte aligned), which holds the
+ * spins in the column layout; no best-seen energy.  Returns
+ * SG_EUNSUPPORTED for other L.
+ * sa_anneal takes this path by itself when L > SG_LDS_MAX_L, emin is NULL,
+ * the single-work-group kernel selected for L would launch fewer than
+ * SG_WIDE_MAX_GROUPS replica groups (so it would leave most compute units
+ * idle), and the workspace holds sg_sa_wide_workspace_bytes(L, n_rep)
+ * bytes; that function returns 0 when sa_anneal would not take the path. */
+#define SG_WIDE_MAX_GROUPS 128
+int sg_sa_anneal_wide(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
+                      int8_t *spins, int32_t *energy, void *stream);
+size_t sg_sa_wide_workspace_bytes(int32_t L, int32_t n_rep);
+
 /* Parallel tempering (App. D): n_runs independent runs of T walkers on an
  * ascending beta ladder.  Step t: every walker w makes one sweep with the
  * thresholds of its ladder slot pos[w] (Metropolis counter (., 2t+c, w,

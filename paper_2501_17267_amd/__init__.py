@@ -107,6 +107,9 @@ def lib() -> ctypes.CDLL:
     L.sg_make_instance.argtypes = [c.c_int32, c.c_int32, c.c_uint64, vp, vp, vp]
     L.sg_sa_workspace_bytes.restype = c.c_size_t
     L.sg_sa_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
+    L.sg_sa_wide_workspace_bytes.restype = c.c_size_t
+    L.sg_sa_wide_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
+    L.sg_sa_anneal_wide.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp]
     L.sg_jenc_bytes.restype = c.c_size_t
     L.sg_jenc_bytes.argtypes = [c.c_int32]
     L.sg_encode_instance.argtypes = [c.POINTER(sg_instance), vp, vp]
@@ -129,7 +132,7 @@ def lib() -> ctypes.CDLL:
     for fn in ("sg_sa_variants", "sg_sa_select_variant", "sg_sa_selected_variant",
                "sg_sa_anneal_variant", "sg_autotune_sa", "sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
-               "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal",
+               "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
                "pt_run", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
@@ -262,9 +265,11 @@ def check_instance(inst: Instance, stream=None) -> int:
 
 
 def _workspace(L: int, n_rep: int, device):
-    """Device scratch for lattices that do not fit in LDS (L > 32), else None."""
+    """Device scratch: required for lattices whose spins do not fit in LDS
+    (L > 32); for few replicas of L > 24 it lets sa_anneal spread the anneal
+    over the whole device.  None when neither applies."""
     import torch
-    nbytes = sa_workspace_bytes(L, n_rep)
+    nbytes = max(sa_workspace_bytes(L, n_rep), sa_wide_workspace_bytes(L, n_rep))
     if nbytes == 0:
         return None
     return torch.empty(nbytes // 4, dtype=torch.int32, device=device)
@@ -344,6 +349,31 @@ def sa_variants(L: int) -> list[dict]:
 
 def sa_workspace_bytes(L: int, n_rep: int) -> int:
     return int(lib().sg_sa_workspace_bytes(L, n_rep))
+
+
+def sa_wide_workspace_bytes(L: int, n_rep: int) -> int:
+    return int(lib().sg_sa_wide_workspace_bytes(L, n_rep))
+
+
+def sa_anneal_wide(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0: int = 0,
+                   spins=None, stream=None):
+    """sa_anneal on the multi-work-group path (L = 26..32, 64), whatever
+    n_rep is.  Returns (spins, energy); results equal sa_anneal's."""
+    import torch
+    dev = inst.J.device
+    L = inst.L
+    N = L ** 3
+    S, K = int(thr.shape[0]), int(thr.shape[1])
+    init_random = spins is None
+    sp = torch.empty((n_rep, N), dtype=torch.int8, device=dev) if init_random else spins
+    en = torch.empty(n_rep, dtype=torch.int32, device=dev)
+    ws = torch.empty(n_rep * L * L * ((L + 3) // 4), dtype=torch.int32, device=dev)
+    args = sg_sa_args(n_rep=n_rep, rep0=rep0, n_sweeps=S, sweep0=sweep0, K=K,
+                      init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _with_workspace(args, ws)
+    _check(lib().sg_sa_anneal_wide(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                                   _dptr(sp, "spins"), _dptr(en, "energy"), _stream(stream)), "sg_sa_anneal_wide")
+    return sp, en
 
 
 def select_variant(L: int, variant: int) -> None:

@@ -179,6 +179,17 @@ void sa_fill_job(SaJob &job, const sg_sa_job &j)
     fill_job(job, &j.inst, &j.args, j.thr, j.spins, j.energy, j.emin);
 }
 
+// sa_anneal's own choice of the multi-work-group path: the selected
+// single-work-group kernel would launch too few groups to fill the device
+static bool wide_auto(int L, int n_rep)
+{
+    int n = 0;
+    const SaVariant *vs = sa_variants(L, &n);
+    if (!vs || n_rep < 1 || !wide_supported(L)) return false;
+    const int rpw = vs[sa_selected(L)].rpw;
+    return (n_rep + rpw - 1) / rpw < SG_WIDE_MAX_GROUPS;
+}
+
 static int run_variant(const SaVariant &v, const SaJob &job, hipStream_t st)
 {
     const int groups = (job.n_rep + v.rpw - 1) / v.rpw;
@@ -202,7 +213,36 @@ int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *t
     SaJob job;
     fill_job(job, inst, args, thr, spins, energy, emin);
     clear_error();
+    // few replicas of a large lattice: spread over the device
+    const int L = inst->L;
+    if (!emin && wide_auto(L, args->n_rep) && args->workspace &&
+        (reinterpret_cast<uintptr_t>(args->workspace) & 15u) == 0 &&
+        args->workspace_bytes >= static_cast<int64_t>(wide_bytes(L, args->n_rep)))
+        return sa_wide(job, L, static_cast<hipStream_t>(stream));
     return run_variant(vs[sa_selected(inst->L)], job, static_cast<hipStream_t>(stream));
+}
+
+int sg_sa_anneal_wide(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr, int8_t *spins,
+                      int32_t *energy, void *stream)
+{
+    const int rc = check_sa_args("sg_sa_anneal_wide", inst, args, thr, spins, energy);
+    if (rc != SG_OK) return rc;
+    if (!wide_supported(inst->L))
+        return fail(SG_EUNSUPPORTED, "sg_sa_anneal_wide: L = %d (the wide path covers L = 26..32 and 64)", inst->L);
+    const size_t need = wide_bytes(inst->L, args->n_rep);
+    if (!args->workspace || args->workspace_bytes < static_cast<int64_t>(need))
+        return fail(SG_EINVAL, "sg_sa_anneal_wide: needs a %zu-byte workspace", need);
+    if ((reinterpret_cast<uintptr_t>(args->workspace) & 15u) != 0)
+        return fail(SG_EINVAL, "sg_sa_anneal_wide: workspace must be 16-byte aligned");
+    SaJob job;
+    fill_job(job, inst, args, thr, spins, energy, nullptr);
+    clear_error();
+    return sa_wide(job, inst->L, static_cast<hipStream_t>(stream));
+}
+
+size_t sg_sa_wide_workspace_bytes(int32_t L, int32_t n_rep)
+{
+    return wide_auto(L, n_rep) ? wide_bytes(L, n_rep) : 0;
 }
 
 int sg_sa_variants(int32_t L, int32_t max, sg_sa_variant *out)

@@ -28,4 +28,10 @@ const SaVariant *sa_variants(int L, int *n);
 // currently selected variant index of L (default or autotuned)
 int sa_selected(int L);
 
+// multi-work-group anneal of lattices above the LDS-resident sizes
+// (wide.hip): sizes it covers, the workspace it needs, and the launch
+bool wide_supported(int L);
+size_t wide_bytes(int L, int n_rep);
+int sa_wide(const SaJob &job, int L, hipStream_t stream);
+
 }  // namespace sg

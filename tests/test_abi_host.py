@@ -64,6 +64,21 @@ def test_instance_generator_large_lattice_matches_oracle():
     assert oracle.energy(Jo, go, (64, 64, 64)) == egs
 
 
+def test_wide_workspace_size():
+    # spins of n_rep replicas in the column layout, where the automatic
+    # choice takes the multi-work-group path: the selected single-group
+    # kernel would launch fewer than 128 replica groups
+    for L in (26, 28, 30, 32, 64):
+        C = (L + 3) // 4
+        rpw = sg.sa_variants(L)[sg.selected_variant(L)]["replicas_per_group"]
+        for n in (1, 3, 16, 127 * rpw, 127 * rpw + 1, 128 * rpw):
+            want = n * L * L * C * 4 if -(-n // rpw) < 128 else 0
+            assert sg.sa_wide_workspace_bytes(L, n) == want, (L, n)
+    assert sg.sa_wide_workspace_bytes(24, 1) == 0
+    assert sg.sa_wide_workspace_bytes(40, 1) == 0
+    assert sg.sa_wide_workspace_bytes(32, 0) == 0
+
+
 def test_jenc_size():
     for L in (4, 6, 12, 16, 64):
         H, C = L // 2, (L + 3) // 4
@@ -107,6 +122,22 @@ def test_invalid_arguments_are_refused_on_the_host():
     assert lib.sg_sa_workspace_bytes(32, 3) == 0
     inst.L = 40   # even and in range, but no kernel is built for it
     assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -7
+    # the multi-work-group path: L = 26..32 and 64 only, with a large enough
+    # 16-byte aligned workspace
+    inst.L = 16
+    rc, msg = _bad_call(lib.sg_sa_anneal_wide, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None)
+    assert rc == -7 and "wide" in msg
+    inst.L = 32
+    rc, msg = _bad_call(lib.sg_sa_anneal_wide, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None)
+    assert rc == -1 and "workspace" in msg
+    args.workspace = 0x3000
+    args.workspace_bytes = 4 * 32 * 32 * 8 * 4 - 4
+    assert lib.sg_sa_anneal_wide(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None) == -1
+    args.workspace_bytes += 4
+    args.workspace = 0x3004
+    rc, msg = _bad_call(lib.sg_sa_anneal_wide, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None)
+    assert rc == -1 and "aligned" in msg
+    args.workspace, args.workspace_bytes = None, 0
     inst.jenc = None
     # PT
     inst.L = 12

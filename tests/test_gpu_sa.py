@@ -51,6 +51,36 @@ def test_sa_bit_exact_large_lattices(L):
     _run_and_compare(L, n_rep, 3 if L == 64 else 4, 0xB16 + L, want_emin=True)
 
 
+@pytest.mark.parametrize("L", [26, 28, 30, 32, 64])
+def test_sa_wide_path_bit_exact(L):
+    # few replicas without the best-seen energy: sa_anneal spreads each
+    # colour phase over the device (one lane per column dword)
+    n_rep = {26: 3, 28: 2, 30: 3, 32: 2, 64: 2}[L]
+    assert sg.sa_wide_workspace_bytes(L, n_rep) > 0
+    _run_and_compare(L, n_rep, 3 if L == 64 else 5, 0xD1DE + L, want_emin=False)
+
+
+@pytest.mark.parametrize("L", [30, 64])
+def test_sa_wide_explicit_offsets_resume_and_equality_with_group_kernel(L):
+    # explicit wide entry point: replica and sweep offsets, a start from
+    # given spins, and equality with the single-work-group kernel
+    inst, Jo, go, egs = instance(L, 0x5EED + L, 4)
+    S = 4 if L == 64 else 6
+    thr = sg.make_thresholds(sg.make_schedule(0, 0.1, 3.0, 2 * S), K)
+    log(f"SA wide explicit L={L}")
+    n_rep = 5
+    a_s, a_e = sg.sa_anneal_wide(inst, dev_u32(thr[:S]), n_rep, 0x77, rep0=9)
+    b_s, b_e = sg.sa_anneal_wide(inst, dev_u32(thr[S:]), n_rep, 0x77, rep0=9, sweep0=S, spins=a_s.clone())
+    g_s, g_e, _ = sg.sa_anneal_variant(inst, dev_u32(thr), n_rep, 0x77, 0, rep0=9)
+    torch.cuda.synchronize()
+    assert torch.equal(b_s, g_s) and torch.equal(b_e, g_e)
+    ref = oracle_sa_parallel(L, Jo, 0x77, 4, thr, [9, 13])
+    sp, en = b_s.cpu().numpy(), b_e.cpu().numpy()
+    for r, rr in ((0, 9), (4, 13)):
+        np.testing.assert_array_equal(sp[r], ref[rr][0])
+        assert en[r] == ref[rr][1]
+
+
 @pytest.mark.parametrize("L", [8, 12])
 def test_sa_bit_exact_without_tracking_and_with_offsets(L):
     _run_and_compare(L, 20, 9, 0xBEE + L, rep0=1000, sweep0=77, want_emin=False)
