@@ -85,6 +85,14 @@ def lib():
         L.orc_metropolis_uniform.restype = c.c_uint32
         L.orc_metropolis_uniform.argtypes = [c.c_int, c.c_uint64, c.c_uint32, c.c_uint32,
                                              c.c_int, c.c_int64]
+        for fn in ("orc_frag_decimate", "orc_frag_decimate_reversed"):
+            getattr(L, fn).restype = c.c_int
+            getattr(L, fn).argtypes = [c.c_int, i8p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                       c.c_uint32, u32p, c.c_int, c.c_int, i8p]
+        L.orc_frag_anneal.restype = c.c_int
+        L.orc_frag_anneal.argtypes = [c.c_int, i8p, c.c_int, c.c_int, c.c_int64, c.c_int, c.c_uint64,
+                                      c.c_uint32, u32p, c.c_int, c.c_int, i8p, i8p,
+                                      c.POINTER(c.c_int64)]
         _lib = L
     return _lib
 
@@ -216,3 +224,31 @@ def pt_run(L, J, seed, run, thr, thrx, n_steps, step0=0, spins=None, pos=None,
                             sw.ctypes.data if sw is not None else None,
                             1 if check else 0), "pt_run")
     return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+
+
+def frag_decimate(L, J, core, halo, R, seed, run, thr, order=1, reversed_order=False) -> np.ndarray:
+    """Fragment decimation (the linear-time meta-heuristic with fixed-sweep SA
+    on fragments, R anneals per fragment); returns the decimated
+    configuration int8 [N]."""
+    thr = np.ascontiguousarray(thr, np.uint32)
+    S, K = thr.shape
+    dec = np.zeros(L ** 3, np.int8)
+    fn = lib().orc_frag_decimate_reversed if reversed_order else lib().orc_frag_decimate
+    _check(fn(L, np.ascontiguousarray(J, np.int8).reshape(-1), core, halo, R, order, seed & 0xFFFFFFFFFFFFFFFF,
+              run, thr.reshape(-1), K, S, dec), "frag_decimate")
+    return dec
+
+
+def frag_anneal(L, J, core, halo, k, rep, seed, run, thr, dec):
+    """Anneal rep of core k with decimation state dec (0 = free); returns
+    (fragment spins int8 [l^3], in-fragment energy)."""
+    thr = np.ascontiguousarray(thr, np.uint32)
+    S, K = thr.shape
+    l = core + 2 * halo
+    frag = np.zeros(l ** 3, np.int8)
+    E = ctypes.c_int64(0)
+    _check(lib().orc_frag_anneal(L, np.ascontiguousarray(J, np.int8).reshape(-1), core, halo, k, rep,
+                                 seed & 0xFFFFFFFFFFFFFFFF, run, thr.reshape(-1), K, S,
+                                 np.ascontiguousarray(dec, np.int8).reshape(-1), frag, ctypes.byref(E)),
+           "frag_anneal")
+    return frag, int(E.value)

@@ -542,3 +542,181 @@ int orc_pt_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
     free(who);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* fragment decimation (Sec. I: bootstrapped subsystem optimisation with a   */
+/* fixed-time stochastic optimiser; App. C: fragments overlapping earlier    */
+/* decimations, non-overlapping fragments processed together)               */
+/* ------------------------------------------------------------------------ */
+
+/* the colour-class order needs nb % P == 0 so that cores of one class stay
+ * P cores apart across the periodic wrap; the wavefront order needs nothing */
+static int frag_params_ok(int L, int c, int h, int order)
+{
+    int l = c + 2 * h, nb, P;
+    if (L < 4 || L % 2 || c < 1 || h < 0 || L % c || l >= L) return 0;
+    nb = L / c;
+    P = 1 + (h + c - 1) / c;
+    return order != 0 || nb % P == 0;
+}
+
+static uint32_t frag_word0(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    uint32_t ctr[4], out[4];
+    ctr[0] = c0;
+    ctr[1] = c1;
+    ctr[2] = c2;
+    ctr[3] = c3;
+    orc_philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
+    return out[0];
+}
+
+int orc_frag_anneal(int L, const int8_t *J, int core, int halo, int64_t k, int rep, uint64_t seed,
+                    uint32_t run, const uint32_t *thr, int K, int S, const int8_t *dec,
+                    int8_t *frag, int64_t *E_frag)
+{
+    int l = core + 2 * halo, nb, bx, by, bz, lx, ly, lz, d, s, col;
+    int64_t N = (int64_t)L * L * L, n3, j, E;
+    int64_t *g;
+    int8_t *fixed;
+    uint32_t w0;
+    if (!frag_params_ok(L, core, halo, 1) || K < 1 || S < 0 || rep < 0) return -1;
+    nb = L / core;
+    if (k < 0 || k >= (int64_t)nb * nb * nb) return -1;
+    bx = (int)(k % nb);
+    by = (int)((k / nb) % nb);
+    bz = (int)(k / ((int64_t)nb * nb));
+    n3 = (int64_t)l * l * l;
+    w0 = (uint32_t)rep * (uint32_t)n3;   /* counter word 0 = rep l^3 + j */
+    g = (int64_t *)malloc(sizeof(int64_t) * (size_t)n3);
+    fixed = (int8_t *)malloc((size_t)n3);
+    if (!g || !fixed) return -3;
+    /* fragment sites, their global index and state */
+    for (lz = 0; lz < l; ++lz)
+        for (ly = 0; ly < l; ++ly)
+            for (lx = 0; lx < l; ++lx) {
+                j = lx + (int64_t)l * (ly + (int64_t)l * lz);
+                g[j] = orc_site(L, L, L, wrap(bx * core - halo + lx, L), wrap(by * core - halo + ly, L),
+                                wrap(bz * core - halo + lz, L));
+                fixed[j] = dec[g[j]] != 0;
+                if (fixed[j])
+                    frag[j] = dec[g[j]];
+                else
+                    frag[j] = (frag_word0(seed, w0 + (uint32_t)j, 0xFFFFFFFFu, (uint32_t)k, run) >> 31) ? -1 : 1;
+            }
+    /* sweeps over the free sites, colour by colour */
+    for (s = 0; s < S; ++s)
+        for (col = 0; col < 2; ++col)
+            for (j = 0; j < n3; ++j) {
+                int x, y, z;
+                int64_t hfield = 0, kk;
+                int acc;
+                if (fixed[j]) continue;
+                coords(L, L, g[j], &x, &y, &z);
+                if ((x + y + z) % 2 != col) continue;
+                lx = (int)(j % l);
+                ly = (int)((j / l) % l);
+                lz = (int)(j / ((int64_t)l * l));
+                for (d = 0; d < 6; ++d) {
+                    int mx = lx + (d == 0) - (d == 1), my = ly + (d == 2) - (d == 3), mz = lz + (d == 4) - (d == 5);
+                    if (mx < 0 || mx >= l || my < 0 || my >= l || mz < 0 || mz >= l) continue; /* bond leaves */
+                    hfield += (int64_t)J[(int64_t)d * N + g[j]] * frag[mx + (int64_t)l * (my + (int64_t)l * mz)];
+                }
+                kk = -(int64_t)frag[j] * hfield;
+                if (kk <= 0)
+                    acc = 1;
+                else
+                    acc = kk <= K && frag_word0(seed, w0 + (uint32_t)j, (uint32_t)(2 * s + col), (uint32_t)k,
+                                                run) < thr[(int64_t)s * K + (kk - 1)];
+                if (acc) frag[j] = (int8_t)(-frag[j]);
+            }
+    /* energy of the in-fragment bonds (+x, +y, +z partners inside) */
+    E = 0;
+    for (j = 0; j < n3; ++j) {
+        lx = (int)(j % l);
+        ly = (int)((j / l) % l);
+        lz = (int)(j / ((int64_t)l * l));
+        if (lx + 1 < l) E += (int64_t)J[0 * N + g[j]] * frag[j] * frag[j + 1];
+        if (ly + 1 < l) E += (int64_t)J[2 * N + g[j]] * frag[j] * frag[j + l];
+        if (lz + 1 < l) E += (int64_t)J[4 * N + g[j]] * frag[j] * frag[j + (int64_t)l * l];
+    }
+    *E_frag = E;
+    free(g);
+    free(fixed);
+    return 0;
+}
+
+/* phase of core (bx, by, bz): order 0 = colour classes
+ * (bx mod P) + P((by mod P) + P(bz mod P)); order 1 = diagonal wavefront
+ * bx + by + bz */
+static int frag_phase(int order, int P, int bx, int by, int bz)
+{
+    return order == 0 ? (bx % P) + P * ((by % P) + P * (bz % P)) : bx + by + bz;
+}
+
+static int frag_common(int L, const int8_t *J, int core, int halo, int R, int order, uint64_t seed,
+                       uint32_t run, const uint32_t *thr, int K, int S, int8_t *dec, int reversed)
+{
+    int l = core + 2 * halo, nb, P, q, r, nq;
+    int64_t N = (int64_t)L * L * L, ncores, n, i;
+    int8_t *frag, *best, *snap;
+    if (order < 0 || order > 1 || !frag_params_ok(L, core, halo, order) || K < 1 || S < 0 || R < 1) return -1;
+    nb = L / core;
+    P = 1 + (halo + core - 1) / core;
+    nq = order == 0 ? P * P * P : 3 * (nb - 1) + 1;
+    ncores = (int64_t)nb * nb * nb;
+    frag = (int8_t *)malloc((size_t)l * l * l);
+    best = (int8_t *)malloc((size_t)l * l * l);
+    snap = (int8_t *)malloc((size_t)N);
+    if (!frag || !best || !snap) return -3;
+    for (i = 0; i < N; ++i) dec[i] = 0;
+    for (q = 0; q < nq; ++q) {
+        /* every core of a phase sees the decimation state at the start of
+         * the phase */
+        memcpy(snap, dec, (size_t)N);
+        for (n = 0; n < ncores; ++n) {
+            int64_t k = reversed ? ncores - 1 - n : n, E, Ebest = INT64_MAX;
+            int bx = (int)(k % nb), by = (int)((k / nb) % nb), bz = (int)(k / ((int64_t)nb * nb));
+            int cx, cy, cz;
+            if (frag_phase(order, P, bx, by, bz) != q) continue;
+            /* R independent anneals of the fragment; the lowest fragment
+             * energy wins (the first replica among equals) */
+            for (r = 0; r < R; ++r) {
+                if (orc_frag_anneal(L, J, core, halo, k, r, seed, run, thr, K, S, snap, frag, &E)) {
+                    free(frag);
+                    free(best);
+                    free(snap);
+                    return -1;
+                }
+                if (E < Ebest) {
+                    Ebest = E;
+                    memcpy(best, frag, (size_t)l * l * l);
+                }
+            }
+            /* the core sits at offset halo inside the fragment */
+            for (cz = 0; cz < core; ++cz)
+                for (cy = 0; cy < core; ++cy)
+                    for (cx = 0; cx < core; ++cx) {
+                        int64_t j = (halo + cx) + (int64_t)l * ((halo + cy) + (int64_t)l * (halo + cz));
+                        dec[orc_site(L, L, L, bx * core + cx, by * core + cy, bz * core + cz)] = best[j];
+                    }
+        }
+    }
+    free(frag);
+    free(best);
+    free(snap);
+    return 0;
+}
+
+int orc_frag_decimate(int L, const int8_t *J, int core, int halo, int R, int order, uint64_t seed,
+                      uint32_t run, const uint32_t *thr, int K, int S, int8_t *dec)
+{
+    return frag_common(L, J, core, halo, R, order, seed, run, thr, K, S, dec, 0);
+}
+
+int orc_frag_decimate_reversed(int L, const int8_t *J, int core, int halo, int R, int order,
+                               uint64_t seed, uint32_t run, const uint32_t *thr, int K, int S,
+                               int8_t *dec)
+{
+    return frag_common(L, J, core, halo, R, order, seed, run, thr, K, S, dec, 1);
+}

@@ -23,6 +23,9 @@
  *               in its references)
  *   Boltzmann   App. A: the target law p(s) ~ exp(-beta H(s)) that fixes
  *               the Metropolis acceptance min(1, exp(-beta dE))
+ *   frag_*      Sec. I and App. C: the bootstrapped subsystem-optimisation
+ *               meta-heuristic, with fixed-sweep simulated annealing as the
+ *               subsystem optimiser on overlapping cubic fragments
  *
  * Parity pins for every function live in tests/test_oracle_*.py; no function
  * here is "parity unpinned".
@@ -109,6 +112,47 @@ int orc_pt_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
                int n_steps, int step0, int init_random,
                int8_t *spins, int64_t *energy, int32_t *pos,
                int64_t *emin_trace, uint32_t *swap_acc, int check);
+
+/* ---- fragment decimation (Sec. I, App. C) ----------------------------------
+ * The linear-time meta-heuristic with fixed-sweep simulated annealing as the
+ * subsystem optimiser.  The lattice (L even) is tiled by cores of c^3 spins
+ * (L % c == 0, nb = L/c cores per axis, core k = bx + nb (by + nb bz) covers
+ * [bx c, bx c + c) x ...).  The fragment of core k is the l^3 cube, l = c+2h
+ * < L, that extends the core by h sites on every side (periodic).  Cores are
+ * processed in phases q = 0, 1, ...; all cores of a phase see the decimation
+ * state at the start of the phase.  order 0: q = (bx mod P) + P((by mod P) +
+ * P (bz mod P)), P = 1 + ceil(h/c), nb % P == 0 (colour classes: no core of
+ * a phase lies in another's fragment); order 1: q = bx + by + bz (a diagonal
+ * wavefront: every core sees the decimated cores on its lower side).
+ * Processing core k of run `run`: R independent anneals r of the fragment,
+ * each as follows, with fragment site j = lx + l (ly + l lz):
+ *   - site j is fixed (a boundary field) if it was decimated before the
+ *     phase, else free;
+ *   - bonds with both ends in the fragment count, all others are dropped;
+ *   - free spins start from bit 31 of Philox word 0 of
+ *     (r l^3 + j, 0xFFFFFFFF, k, run) (set: -1);
+ *   - S sweeps: colour (x+y+z) mod 2 = 0 then 1, a Metropolis proposal at
+ *     every free site of that colour: k_i = -s_i h_i (in-fragment bonds),
+ *     flip iff k_i <= 0 or (k_i <= K and u < thr[s*K + k_i - 1]), u = Philox
+ *     word 0 of (r l^3 + j, 2s + colour, k, run);
+ * then the core's spins take their final values in the anneal whose
+ * in-fragment energy is lowest (the smallest r among equals): they are
+ * decimated.
+ * dec[N] (output) holds every spin, +1/-1.  Returns 0, or -1 on bad input. */
+int orc_frag_decimate(int L, const int8_t *J, int core, int halo, int R, int order, uint64_t seed,
+                      uint32_t run, const uint32_t *thr, int K, int S, int8_t *dec);
+/* The same with the cores of each phase visited in reverse order (the
+ * result must not depend on the order inside a phase). */
+int orc_frag_decimate_reversed(int L, const int8_t *J, int core, int halo, int R, int order,
+                               uint64_t seed, uint32_t run, const uint32_t *thr, int K, int S,
+                               int8_t *dec);
+/* Anneal r of core k as above with decimation state dec (0 = not yet
+ * decimated; left unchanged).  frag[l^3] receives the final fragment spins
+ * (fixed ones included), *E_frag the energy of the in-fragment bonds (each
+ * once). */
+int orc_frag_anneal(int L, const int8_t *J, int core, int halo, int64_t k, int rep, uint64_t seed,
+                    uint32_t run, const uint32_t *thr, int K, int S, const int8_t *dec,
+                    int8_t *frag, int64_t *E_frag);
 
 /* ---- initial spins (init stream) ------------------------------------------ */
 void orc_init_spins(int L, uint64_t seed, uint32_t chain, uint32_t replica, int8_t *s);
