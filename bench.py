@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "microbench",
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "microbench",
                              "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
@@ -166,6 +166,31 @@ def cpu_baseline_sa(w, thr_h, target_s):
                       f"({attempts:.3g} attempts in {dt:.1f} s)"}
 
 
+def cpu_baseline_fragment(sg, wl, L=12):
+    """The oracle's fragment decimation of L = 12 instances of the measured
+    workload (first setting), one instance per host thread."""
+    import concurrent.futures as cf
+
+    import oracle
+    st = wl.fragment_settings()[0]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    thr = oracle.thresholds(oracle.schedule(0, st.beta0, st.beta1, st.n_sweeps), sg.SG_K_MAX)
+    specs = wl.fragment_instances(L, cores)
+    Js = [oracle.make_instance(L, s.cls, s.seed)[0] for s in specs]
+    seed = wl.philox_seed("fragment")
+
+    def one(k):
+        oracle.frag_decimate(L, Js[k], st.core, st.halo, st.replicas, seed, k, thr, order=st.order)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, range(cores)))
+    dt = time.perf_counter() - t0
+    proposals = cores * (L ** 3 // st.core ** 3) * st.replicas * (st.core + 2 * st.halo) ** 3 * st.n_sweeps
+    return {"value": cores / dt, "unit": f"instances/s at L={L} ({st.name})", "cores": cores, "kind": "oracle",
+            "proposals_per_s": proposals / dt,
+            "sample": f"{cores} instances at L={L}, one per thread, {dt:.1f} s"}
+
+
 # ---------------------------------------------------------------------------
 
 def main():
@@ -193,6 +218,9 @@ def main():
     if a.workload != "sa_batch":
         from paper_2501_17267_amd import benchmarks
         out = benchmarks.run(a.workload, a, sg, wl, torch)
+        if a.workload == "fragment" and not a.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_fragment(sg, wl)
         print(json.dumps(out))
         return
 

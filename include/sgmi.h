@@ -166,6 +166,50 @@ int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
            const uint32_t *thrx, int8_t *spins, int32_t *energy, int32_t *pos,
            int32_t *emin_trace, uint32_t *swap_acc, void *stream);
 
+/* ---- the linear-time meta-heuristic (Sec. I) with simulated annealing as the
+ * subsystem optimiser, bootstrapped over overlapping fragments (App. C) ----
+ * The lattice is tiled by cores of c^3 spins (L % c == 0, nb = L/c per axis,
+ * core k = bx + nb (by + nb bz)); the fragment of a core is the l^3 cube,
+ * l = c + 2h, that extends it by h sites on every side (periodic).  Cores
+ * are decimated phase by phase; all cores of a phase run at once and see
+ * the decimation state at the start of their phase:
+ *   order 0: phase (bx mod P) + P((by mod P) + P(bz mod P)), P = 1 +
+ *            ceil(h/c), nb % P == 0 (colour classes: no core of a phase lies
+ *            in another's fragment);
+ *   order 1: phase bx + by + bz (a diagonal wavefront: each core sees the
+ *            decimated cores below it).
+ * A core is processed by R independent anneals of its fragment.  Site j =
+ * lx + l (ly + l lz) is fixed (a boundary field) when it was decimated in
+ * an earlier phase, else free; only bonds with both ends in the fragment
+ * count.  Anneal r starts its free spins from bit 31 of Philox word 0 of
+ * (r l^3 + j, 0xFFFFFFFF, k, run) (set: -1) and makes n_sweeps sweeps
+ * (colour (x+y+z) mod 2 = 0, then 1) of Metropolis proposals at its free
+ * sites with u = Philox word 0 of (r l^3 + j, 2s + colour, k, run) against
+ * thr row s (as sa_anneal).  The anneal with the lowest in-fragment energy
+ * (lowest r among equals) gives the core's spins.  The time is linear in
+ * N: N/c^3 fragments of fixed cost. */
+#define SG_FRAG_MAX_L 9      /* largest fragment edge l */
+#define SG_FRAG_MAX_R 16     /* most anneals per fragment */
+typedef struct sg_frag_args {
+    int32_t core;       /* c >= 1, divides L */
+    int32_t halo;       /* h >= 0; l = c + 2h < L and <= SG_FRAG_MAX_L */
+    int32_t replicas;   /* R anneals per fragment, 1..SG_FRAG_MAX_R */
+    int32_t order;      /* 0 colour classes, 1 diagonal wavefront */
+    int32_t n_runs;     /* independent decimations; run j uses counter word run0 + j */
+    uint32_t run0;
+    int32_t n_sweeps;   /* sweeps per fragment anneal = rows of thr */
+    int32_t K;          /* row length of thr, 1..SG_K_MAX */
+    uint64_t seed;      /* Philox key */
+} sg_frag_args;
+
+/* inst->J (natural order) is required.  thr: device uint32 [n_sweeps][K];
+ * spins_out: device int8 [n_runs][N], the decimated configurations (+-1);
+ * energy_out: device int32 [n_runs] or NULL, their energies (Eq. 1).
+ * SG_EINVAL for shapes outside the rules above, SG_ERANGE when the run
+ * counter words overflow or n_runs * nb^3 exceeds one launch. */
+int sg_fragment_decimate(const sg_instance *inst, const sg_frag_args *args, const uint32_t *thr,
+                         int8_t *spins_out, int32_t *energy_out, void *stream);
+
 /* Energy (Eq. 1) of n_rep configurations spins [n_rep][N] -> energy [n_rep]. */
 int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t *energy_out,
            void *stream);

@@ -52,6 +52,12 @@ class sg_sa_job(ctypes.Structure):
                 ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("emin", ctypes.c_void_p)]
 
 
+class sg_frag_args(ctypes.Structure):
+    _fields_ = [("core", ctypes.c_int32), ("halo", ctypes.c_int32), ("replicas", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
+                ("n_sweeps", ctypes.c_int32), ("K", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class sg_sa_variant(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("replicas_per_group", ctypes.c_int32),
                 ("waves_per_group", ctypes.c_int32), ("both_encodings", ctypes.c_int32),
@@ -117,6 +123,7 @@ def lib() -> ctypes.CDLL:
     L.sa_anneal.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp, vp]
     L.pt_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), vp, vp, vp, vp, vp, vp, vp, vp]
     L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
+    L.sg_fragment_decimate.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_frag_args), vp, vp, vp, vp]
     L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
     L.sg_batch_create.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
     L.sg_batch_launch.argtypes = [vp, vp]
@@ -133,6 +140,7 @@ def lib() -> ctypes.CDLL:
                "sg_sa_anneal_variant", "sg_autotune_sa", "sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
+               "sg_fragment_decimate",
                "pt_run", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
@@ -435,6 +443,26 @@ def load_tuning(path: str) -> dict:
     for L, v in choice.items():
         select_variant(L, v)
     return choice
+
+
+def fragment_decimate(inst: Instance, thr, core: int, halo: int, replicas: int, order: int, n_runs: int,
+                      seed: int, run0: int = 0, stream=None):
+    """The linear-time meta-heuristic: decimate every core of c^3 spins from
+    the best of `replicas` anneals of its (c + 2 halo)^3 fragment, phase by
+    phase (order 0 colour classes, 1 diagonal wavefront).  thr: device uint32
+    [n_sweeps][K].  Returns (spins int8 [n_runs][N], energy int32 [n_runs])."""
+    import torch
+    dev = inst.J.device
+    N = inst.L ** 3
+    S, K = int(thr.shape[0]), int(thr.shape[1])
+    sp = torch.empty((n_runs, N), dtype=torch.int8, device=dev)
+    en = torch.empty(n_runs, dtype=torch.int32, device=dev)
+    args = sg_frag_args(core=core, halo=halo, replicas=replicas, order=order, n_runs=n_runs, run0=run0,
+                        n_sweeps=S, K=K, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _check(lib().sg_fragment_decimate(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                                      _dptr(sp, "spins"), _dptr(en, "energy"), _stream(stream)),
+           "sg_fragment_decimate")
+    return sp, en
 
 
 def energy(inst: Instance, spins, stream=None):

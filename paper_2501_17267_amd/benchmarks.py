@@ -219,7 +219,16 @@ def tteps(a, sg, wl, torch):
     return res
 
 
+def fragment(a, sg, wl, torch):
+    """eps_lin and time per instance of the linear-time meta-heuristic vs L."""
+    from . import fragment as fr
+    import sys
+    res = fr.run(torch, log=lambda *m: print("[fragment]", *m, file=sys.stderr, flush=True))
+    res["metric"] = "eps_lin and time per instance of the fragment meta-heuristic vs L"
+    return res
+
+
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps}[name]
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment}[name]
     return fn(a, sg, wl, torch)

@@ -2,6 +2,7 @@
 // instance validation kernels with their C-ABI entry points.
 #include "common.hpp"
 #include "sweep.hpp"
+#include "variants.hpp"
 
 namespace sg {
 
@@ -109,6 +110,19 @@ static int check_launch(const char *what)
 
 using namespace sg;
 
+namespace sg {
+
+int launch_energy(const int8_t *J, int L, int n, const int8_t *spins, int32_t *out, hipStream_t stream)
+{
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_energy, dim3(static_cast<uint32_t>(n)), dim3(kEnergyThreads), 0, stream, J, L, spins, out);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(SG_EDEVICE, "energy: launch failed: %s", hipGetErrorString(err));
+    return SG_OK;
+}
+
+}  // namespace sg
+
 extern "C" {
 
 int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t *energy_out, void *stream)
@@ -117,10 +131,7 @@ int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t 
     if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "energy: L = %d", inst->L);
     if (n_rep < 1) return fail(SG_EINVAL, "energy: n_rep = %d", n_rep);
     clear_error();
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_energy, dim3(n_rep), dim3(kEnergyThreads), 0, static_cast<hipStream_t>(stream),
-                       inst->J, inst->L, spins, energy_out);
-    return check_launch("energy");
+    return launch_energy(inst->J, inst->L, n_rep, spins, energy_out, static_cast<hipStream_t>(stream));
 }
 
 int epsilon(const int32_t *energy_in, int64_t n, int64_t E_gs, double *eps_out, void *stream)

@@ -28,6 +28,9 @@ const SaVariant *sa_variants(int L, int *n);
 // currently selected variant index of L (default or autotuned)
 int sa_selected(int L);
 
+// energies (Eq. 1) of n configurations in natural order (aux.hip)
+int launch_energy(const int8_t *J, int L, int n, const int8_t *spins, int32_t *out, hipStream_t stream);
+
 // multi-work-group anneal of lattices above the LDS-resident sizes
 // (wide.hip): sizes it covers, the workspace it needs, and the launch
 bool wide_supported(int L);

@@ -24,7 +24,7 @@ MASTER_SEED = 0x250117267
 MASK64 = (1 << 64) - 1
 T6 = 6  # class code: number of frustrated faces per tile
 
-WORKLOAD_IDS = {"sa_small": 1, "sa_batch": 2, "pt": 3, "uneven": 4, "serve": 5}
+WORKLOAD_IDS = {"sa_small": 1, "sa_batch": 2, "pt": 3, "uneven": 4, "serve": 5, "fragment": 6}
 
 
 def mix64(x: int) -> int:
@@ -118,3 +118,27 @@ def uneven(n_inst=4096, n_rep=64, sizes=(6, 8, 10, 12, 16, 20),
 
 def uneven_seed() -> int:
     return philox_seed("uneven")
+
+
+@dataclass(frozen=True)
+class FragmentSetting:
+    name: str
+    core: int
+    halo: int
+    replicas: int
+    n_sweeps: int
+    order: int = 1          # diagonal wavefront
+    beta0: float = 0.1
+    beta1: float = 3.0
+
+
+def fragment_settings():
+    """The meta-heuristic as measured: the paper's fragment edge l = 5 with
+    one decimated spin per fragment, and a cheaper block form (2^3 cores in
+    4^3 fragments)."""
+    return (FragmentSetting("l5_single_spin", 1, 2, 8, 100),
+            FragmentSetting("l4_block8", 2, 1, 8, 50))
+
+
+def fragment_instances(L: int, n: int = 20):
+    return tuple(InstanceSpec(L, instance_seed("fragment", 1000 * L + k), k) for k in range(n))

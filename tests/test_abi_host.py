@@ -139,6 +139,28 @@ def test_invalid_arguments_are_refused_on_the_host():
     assert rc == -1 and "aligned" in msg
     args.workspace, args.workspace_bytes = None, 0
     inst.jenc = None
+    # fragment decimation: shape rules checked before any launch
+    inst.L = 12
+    inst.J = 0x1000
+    fa = sg.sg_frag_args(core=1, halo=2, replicas=4, order=1, n_runs=2, n_sweeps=10, K=24, seed=1)
+    for field, bad in (("core", 5), ("halo", 6), ("replicas", 17), ("replicas", 0), ("order", 2),
+                       ("n_runs", 0), ("K", 25)):
+        old = getattr(fa, field)
+        setattr(fa, field, bad)
+        rc, msg = _bad_call(lib.sg_fragment_decimate, ctypes.byref(inst), ctypes.byref(fa), fake, fake, None, None)
+        assert rc == -1, (field, bad, rc, msg)
+        setattr(fa, field, old)
+    fa.core, fa.halo, fa.order = 4, 1, 0   # 3 cores per axis cannot be 2-coloured
+    rc, msg = _bad_call(lib.sg_fragment_decimate, ctypes.byref(inst), ctypes.byref(fa), fake, fake, None, None)
+    assert rc == -1 and "divisible" in msg
+    fa.core, fa.halo, fa.order = 1, 4, 1   # l = 9 is allowed at L = 12, l = 11 is not
+    fa.halo = 5
+    assert lib.sg_fragment_decimate(ctypes.byref(inst), ctypes.byref(fa), fake, fake, None, None) == -1
+    fa.halo, fa.run0 = 2, 0xFFFFFFFF
+    assert lib.sg_fragment_decimate(ctypes.byref(inst), ctypes.byref(fa), fake, fake, None, None) == -4
+    inst.J = None
+    fa.run0 = 0
+    assert lib.sg_fragment_decimate(ctypes.byref(inst), ctypes.byref(fa), fake, fake, None, None) == -1
     # PT
     inst.L = 12
     pargs = sg.sg_pt_args(n_runs=2, T=1, n_steps=5, K=24, M=10, init_random=1, seed=3)
