@@ -228,7 +228,17 @@ def fragment(a, sg, wl, torch):
     return res
 
 
+def tuning(a, sg, wl, torch):
+    """App. D form: SA beta-range grid, PT ladder grid, then alpha(eps) at
+    eps = 3, 4, 5 % for SA and PT with the chosen parameters."""
+    from . import tuning as tu
+    import sys
+    res = tu.run(torch, log=lambda *m: print("[tuning]", *m, file=sys.stderr, flush=True))
+    res["metric"] = "tuned SA/PT parameters and alpha(eps) at eps = 3, 4, 5%"
+    return res
+
+
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment}[name]
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tuning": tuning}[name]
     return fn(a, sg, wl, torch)

@@ -37,14 +37,17 @@ def sweep_grid(lo=16, hi=32768):
         k += 1
 
 
-def _thr(cache, S):
-    if S not in cache:
-        cache[S] = to_device_u32(make_thresholds(make_schedule(0, 0.1, 3.0, S)))
-    return cache[S]
+def _thr(cache, S, schedule=(0, 0.1, 3.0)):
+    key = (S,) + tuple(schedule)
+    if key not in cache:
+        kind, b0, b1 = schedule
+        cache[key] = to_device_u32(make_thresholds(make_schedule(kind, b0, b1, S)))
+    return cache[key]
 
 
-def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, targets=(0.01, 0.03, 0.05),
-        s_max=32768, log=print, served=True, plain_inst=5):
+def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, targets=(0.01, 0.03, 0.04, 0.05),
+        s_max=32768, log=print, served=True, plain_inst=5, schedule=(0, 0.1, 3.0)):
+    """schedule: (kind, beta0, beta1) of every anneal (0 linear, 1 geometric)."""
     seed = wl.philox_seed("serve") ^ 0x77
     thr_cache = {}
     grid = sweep_grid(hi=s_max)
@@ -56,7 +59,7 @@ def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, target
         batched_ms = {}
         eps_mean = {}
         for S in grid:
-            jobs = [SAJob(inst, _thr(thr_cache, S), n_trials, seed) for inst in insts]
+            jobs = [SAJob(inst, _thr(thr_cache, S, schedule), n_trials, seed) for inst in insts]
             b = Batch(jobs, graph=False)
             b.launch()
             torch.cuda.synchronize()
@@ -86,7 +89,7 @@ def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, target
             # batched runs); timed on the first plain_inst instances
             plain = []
             for k, inst in enumerate(insts[:plain_inst]):
-                thr = _thr(thr_cache, Ss[k])
+                thr = _thr(thr_cache, Ss[k], schedule)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 sa_anneal(inst, thr, 1, seed)
@@ -97,7 +100,7 @@ def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, target
                      "plain_instances_timed": len(plain),
                      "batched_ms_per_trial": float(np.mean(batched))}
             if served:
-                entry["served_ms"] = _served_latency(torch, insts, Ss, n_trials, seed, thr_cache)
+                entry["served_ms"] = _served_latency(torch, insts, Ss, n_trials, seed, thr_cache, schedule)
             res_L["targets"][str(t)] = entry
         per_L[L] = res_L
     fits = {}
@@ -108,17 +111,17 @@ def run(torch, sizes=(8, 12, 16, 20, 24, 32, 64), n_inst=20, n_trials=20, target
                         for form, key in (("plain", "plain_ms"), ("batched", "batched_ms_per_trial"),
                                           ("served", "served_ms")) if pts and key in pts[0][1]}
     return {"per_L": {str(L): v for L, v in per_L.items()}, "fits": fits,
-            "n_inst": n_inst, "n_trials": n_trials, "grid": grid}
+            "n_inst": n_inst, "n_trials": n_trials, "grid": grid, "schedule": list(schedule)}
 
 
-def _served_latency(torch, insts, Ss, n_trials, seed, thr_cache):
+def _served_latency(torch, insts, Ss, n_trials, seed, thr_cache, schedule):
     from .serving import Server, SG_REQ_DONE
     srv = Server(max_active=8192, chunk_sweeps=512, large_slots=max(8, len(insts) * n_trials),
                  chunk_attempts=1 << 24)
     ids = []
     bufs = []
     for k, inst in enumerate(insts):
-        thr = _thr(thr_cache, Ss[k])
+        thr = _thr(thr_cache, Ss[k], schedule)
         for r in range(n_trials):
             sp = torch.empty(inst.L ** 3, dtype=torch.int8, device="cuda")
             en = torch.empty(1, dtype=torch.int32, device="cuda")
