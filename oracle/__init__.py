@@ -85,6 +85,12 @@ def lib():
         L.orc_metropolis_uniform.restype = c.c_uint32
         L.orc_metropolis_uniform.argtypes = [c.c_int, c.c_uint64, c.c_uint32, c.c_uint32,
                                              c.c_int, c.c_int64]
+        L.orc_pticm_run.restype = c.c_int
+        L.orc_pticm_run.argtypes = [c.c_int, i8p, c.c_uint64, c.c_uint32, c.c_int,
+                                    u32p, c.c_int, u32p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                    i8p, i64p, i32p, c.c_void_p, c.c_void_p, c.c_void_p, c.c_int]
+        L.orc_icm_move.restype = c.c_int64
+        L.orc_icm_move.argtypes = [c.c_int, i8p, i8p, i8p, c.c_uint32]
         for fn in ("orc_frag_decimate", "orc_frag_decimate_reversed"):
             getattr(L, fn).restype = c.c_int
             getattr(L, fn).argtypes = [c.c_int, i8p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
@@ -252,3 +258,44 @@ def frag_anneal(L, J, core, halo, k, rep, seed, run, thr, dec):
                                  np.ascontiguousarray(dec, np.int8).reshape(-1), frag, ctypes.byref(E)),
            "frag_anneal")
     return frag, int(E.value)
+
+
+def pticm_run(L, J, seed, run, thr, thrx, n_steps, icm_from=0, step0=0, spins=None, pos=None,
+              want_trace=False, want_swaps=False, want_icm=False, check=False):
+    """PT with isoenergetic cluster moves: two copies of the T-slot ladder
+    (2T walkers).  Returns dict(spins [2T][N], energy, pos, emin_trace,
+    swap_acc [2(T-1)], icm_flipped)."""
+    N = L ** 3
+    thr = np.ascontiguousarray(thr, np.uint32)
+    thrx = np.ascontiguousarray(thrx, np.uint32)
+    T, K = thr.shape
+    M = thrx.shape[1]
+    W = 2 * T
+    init_random = spins is None
+    sp = np.zeros((W, N), np.int8) if init_random else np.array(spins, np.int8).reshape(W, N)
+    sp = np.ascontiguousarray(sp)
+    ps = np.arange(W, dtype=np.int32) % T if pos is None else np.array(pos, np.int32)
+    ps = np.ascontiguousarray(ps)
+    en = np.zeros(W, np.int64)
+    tr = np.zeros(n_steps, np.int64) if want_trace else None
+    sw = np.zeros(2 * (T - 1), np.uint32) if want_swaps else None
+    ic = np.zeros(n_steps, np.int64) if want_icm else None
+    _check(lib().orc_pticm_run(L, np.ascontiguousarray(J, np.int8).reshape(-1),
+                               seed & 0xFFFFFFFFFFFFFFFF, run, T, thr.reshape(-1), K,
+                               thrx.reshape(-1), M, n_steps, step0, icm_from, 1 if init_random else 0,
+                               sp.reshape(-1), en, ps,
+                               tr.ctypes.data if tr is not None else None,
+                               sw.ctypes.data if sw is not None else None,
+                               ic.ctypes.data if ic is not None else None,
+                               1 if check else 0), "pticm_run")
+    return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw, "icm_flipped": ic}
+
+
+def icm_move(L, J, sa, sb, u):
+    """One cluster move on copies of sa, sb; returns (sa', sb', cluster size)."""
+    a = np.ascontiguousarray(np.array(sa, np.int8).reshape(-1))
+    b = np.ascontiguousarray(np.array(sb, np.int8).reshape(-1))
+    n = lib().orc_icm_move(L, np.ascontiguousarray(J, np.int8).reshape(-1), a, b, u)
+    if n < 0:
+        raise RuntimeError("oracle icm_move failed")
+    return a, b, int(n)

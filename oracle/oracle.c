@@ -720,3 +720,157 @@ int orc_frag_decimate_reversed(int L, const int8_t *J, int core, int halo, int R
 {
     return frag_common(L, J, core, halo, R, order, seed, run, thr, K, S, dec, 1);
 }
+
+/* ------------------------------------------------------------------------ */
+/* parallel tempering with isoenergetic cluster moves (App. D)              */
+/* ------------------------------------------------------------------------ */
+
+int64_t orc_icm_move(int L, const int8_t *J, int8_t *sa, int8_t *sb, uint32_t u)
+{
+    int64_t N = (int64_t)L * L * L, n = 0, idx, seed_site = -1, head, tail, i;
+    int64_t *queue;
+    int8_t *in;
+    int c, col, z, d, H = L / 2;
+    /* negative sites in the order (colour, column, height) */
+    for (c = 0; c < 2; ++c)
+        for (col = 0; col < H * L; ++col)
+            for (z = 0; z < L; ++z) {
+                int y = col / H, x = 2 * (col % H) + ((y + z + c) & 1);
+                i = orc_site(L, L, L, x, y, z);
+                if (sa[i] != sb[i]) ++n;
+            }
+    if (n == 0) return 0;
+    idx = (int64_t)(((uint64_t)u * (uint64_t)n) >> 32);
+    for (c = 0; c < 2 && seed_site < 0; ++c)
+        for (col = 0; col < H * L && seed_site < 0; ++col)
+            for (z = 0; z < L; ++z) {
+                int y = col / H, x = 2 * (col % H) + ((y + z + c) & 1);
+                i = orc_site(L, L, L, x, y, z);
+                if (sa[i] != sb[i] && idx-- == 0) {
+                    seed_site = i;
+                    break;
+                }
+            }
+    /* breadth-first growth through negative sites and nonzero couplings */
+    queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    in = (int8_t *)calloc((size_t)N, 1);
+    if (!queue || !in) return -3;
+    head = tail = 0;
+    queue[tail++] = seed_site;
+    in[seed_site] = 1;
+    while (head < tail) {
+        i = queue[head++];
+        for (d = 0; d < 6; ++d) {
+            int64_t j = orc_nbr(L, L, L, i, d);
+            if (J[(int64_t)d * N + i] == 0 || in[j] || sa[j] == sb[j]) continue;
+            in[j] = 1;
+            queue[tail++] = j;
+        }
+    }
+    for (head = 0; head < tail; ++head) {
+        i = queue[head];
+        sa[i] = (int8_t)(-sa[i]);
+        sb[i] = (int8_t)(-sb[i]);
+    }
+    free(queue);
+    free(in);
+    return tail;
+}
+
+int orc_pticm_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
+                  const uint32_t *thr, int K, const uint32_t *thrx, int M,
+                  int n_steps, int step0, int icm_from, int init_random,
+                  int8_t *spins, int64_t *energy, int32_t *pos,
+                  int64_t *emin_trace, uint32_t *swap_acc, int64_t *icm_flipped, int check)
+{
+    int64_t N = (int64_t)L * L * L;
+    int w, k, ti, cp, W = 2 * T;
+    int32_t *who;   /* who[cp*T + k] = walker of copy cp at slot k */
+    if (L < 4 || L % 2 || T < 2 || K < 1 || M < 1 || n_steps < 0 || step0 < 0 || icm_from < 0) return -1;
+    who = (int32_t *)malloc(sizeof(int32_t) * (size_t)W);
+    if (!who) return -3;
+    if (init_random)
+        for (w = 0; w < W; ++w) {
+            orc_init_spins(L, seed, run, (uint32_t)w, spins + (int64_t)w * N);
+            pos[w] = w % T;
+        }
+    for (k = 0; k < W; ++k) who[k] = -1;
+    for (w = 0; w < W; ++w) {
+        int slot = (w / T) * T + pos[w];
+        if (pos[w] < 0 || pos[w] >= T || who[slot] != -1) {
+            free(who);
+            return -1;
+        }
+        who[slot] = w;
+        energy[w] = orc_energy(L, L, L, J, spins + (int64_t)w * N);
+    }
+    for (ti = 0; ti < n_steps; ++ti) {
+        int t = step0 + ti;
+        int64_t best, flipped = 0;
+        /* 1. sweeps */
+        for (w = 0; w < W; ++w) {
+            int8_t *s = spins + (int64_t)w * N;
+            energy[w] += sweep(L, J, s, thr + (int64_t)pos[w] * K, K, seed, run, (uint32_t)w, t, 0);
+            if (check && energy[w] != orc_energy(L, L, L, J, s)) {
+                free(who);
+                return -2;
+            }
+        }
+        /* 2. cluster moves between the copies, slot by slot */
+        for (k = icm_from; k < T; ++k) {
+            int a = who[k], b = who[T + k];
+            int64_t before = energy[a] + energy[b], size;
+            uint32_t ctr[4], out[4];
+            ctr[0] = (uint32_t)k;
+            ctr[1] = (uint32_t)t;
+            ctr[2] = 0xFFFFFFFEu;
+            ctr[3] = run;
+            orc_philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
+            size = orc_icm_move(L, J, spins + (int64_t)a * N, spins + (int64_t)b * N, out[0]);
+            if (size < 0) {
+                free(who);
+                return -3;
+            }
+            flipped += size;
+            energy[a] = orc_energy(L, L, L, J, spins + (int64_t)a * N);
+            energy[b] = orc_energy(L, L, L, J, spins + (int64_t)b * N);
+            if (check && energy[a] + energy[b] != before) {
+                free(who);
+                return -2;
+            }
+        }
+        /* 3. exchanges inside each copy */
+        for (cp = 0; cp < 2; ++cp)
+            for (k = t % 2; k + 1 < T; k += 2) {
+                int a = who[cp * T + k], b = who[cp * T + k + 1];
+                int64_t D = energy[a] - energy[b];
+                int accept;
+                if (D <= 0) {
+                    accept = 1;
+                } else {
+                    uint32_t ctr[4], out[4];
+                    int64_t m = D / 2;
+                    ctr[0] = (uint32_t)(k + cp * T);
+                    ctr[1] = (uint32_t)t;
+                    ctr[2] = 0xFFFFFFFFu;
+                    ctr[3] = run;
+                    orc_philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
+                    accept = (m <= M) && (out[0] < thrx[(int64_t)k * M + (m - 1)]);
+                }
+                if (accept) {
+                    who[cp * T + k] = b;
+                    who[cp * T + k + 1] = a;
+                    pos[b] = k;
+                    pos[a] = k + 1;
+                    if (swap_acc) swap_acc[cp * (T - 1) + k] += 1;
+                }
+            }
+        best = energy[0];
+        for (w = 1; w < W; ++w)
+            if (energy[w] < best) best = energy[w];
+        if (emin_trace) emin_trace[ti] = best;
+        if (icm_flipped) icm_flipped[ti] = flipped;
+    }
+    free(who);
+    return 0;
+}

@@ -17,6 +17,8 @@
  *               beta schedule, one read = the final configuration
  *   pt_run      App. D (Parallel Tempering): Metropolis sweeps of T walkers
  *               on a ladder of betas plus neighbour replica exchange
+ *   pticm_run   App. D (PT with isoenergetic cluster moves): two copies of
+ *               the ladder plus a cluster move between them per slot
  *   make_inst   Sec. II: tile-planted instance with a gauge-scrambled
  *               planted ground state and exactly known E_gs (synthetic
  *               stand-in: the tile classes of the paper are defined only
@@ -112,6 +114,42 @@ int orc_pt_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
                int n_steps, int step0, int init_random,
                int8_t *spins, int64_t *energy, int32_t *pos,
                int64_t *emin_trace, uint32_t *swap_acc, int check);
+
+/* ---- parallel tempering with isoenergetic cluster moves (App. D) ----------
+ * The paper runs PT with isoenergetic cluster moves (ICM) and only names
+ * the moves.  The move used here is Houdayer's two-replica cluster move as
+ * combined with PT by Zhu, Ochoa and Katzgraber (2015), restated:
+ * two copies of a T-slot ladder, walkers w = 0..2T-1, copy(w) = w / T
+ * (walkers never change copy); pos[w] in [0, T) is the slot of w inside its
+ * copy.  Step t:
+ *   1. every walker makes one sweep with thresholds row pos[w] and
+ *      Metropolis counter (., 2t+c, w, run) (as PT);
+ *   2. for slots k = icm_from .. T-1: the walkers a, b of copy 0 and 1 at
+ *      slot k; sites with s_a != s_b are "negative"; if there are n > 0 of
+ *      them, the seed is the negative site number floor(u n / 2^32) in the
+ *      order (colour, column, height) of the colour-split column layout
+ *      (colour c = (x+y+z) mod 2, column x/2 + (L/2) y, height z), with u =
+ *      Philox word 0 of (k, t, 0xFFFFFFFE, run); the cluster is every
+ *      negative site connected to the seed through negative sites and
+ *      nonzero couplings; both walkers flip the cluster (E_a + E_b is
+ *      unchanged);
+ *   3. in each copy cp, ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ...
+ *      exchange as in PT with u = Philox word 0 of (k + cp T, t, 0xFFFFFFFF,
+ *      run) (copy 0 uses exactly PT's counters).
+ * spins [2T][N], energy [2T], pos [2T] in/out (init_random resets spins from
+ * the init stream with replica word w and pos[w] = w mod T); emin_trace
+ * [n_steps] (minimum over all walkers after the step), swap_acc [2(T-1)]
+ * (copy-major) and icm_flipped [n_steps] (sites flipped per walker by the
+ * cluster moves of the step) are nullable.  check = 1 recomputes energies
+ * after every phase and returns -2 on a mismatch or a change of E_a + E_b. */
+int orc_pticm_run(int L, const int8_t *J, uint64_t seed, uint32_t run, int T,
+                  const uint32_t *thr, int K, const uint32_t *thrx, int M,
+                  int n_steps, int step0, int icm_from, int init_random,
+                  int8_t *spins, int64_t *energy, int32_t *pos,
+                  int64_t *emin_trace, uint32_t *swap_acc, int64_t *icm_flipped, int check);
+/* One cluster move on walkers sa, sb with uniform word u (step 2 above);
+ * returns the cluster size (0 when the walkers agree everywhere). */
+int64_t orc_icm_move(int L, const int8_t *J, int8_t *sa, int8_t *sb, uint32_t u);
 
 /* ---- fragment decimation (Sec. I, App. C) ----------------------------------
  * The linear-time meta-heuristic with fixed-sweep simulated annealing as the
