@@ -166,6 +166,48 @@ int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
            const uint32_t *thrx, int8_t *spins, int32_t *energy, int32_t *pos,
            int32_t *emin_trace, uint32_t *swap_acc, void *stream);
 
+/* ---- parallel tempering with isoenergetic cluster moves (App. D, PT+ICM) ----
+ * The paper only names the cluster moves; this is Houdayer's two-replica
+ * move as combined with PT by Zhu, Ochoa and Katzgraber (2015).  Two copies
+ * of a T-slot ladder: walkers w = 0..2T-1, copy(w) = w / T (fixed), pos[w]
+ * = slot of w inside its copy.  Step t:
+ *   1. every walker makes one sweep (thresholds row pos[w], Metropolis
+ *      counter (., 2t+c, w, run), as pt_run);
+ *   2. for slots k = icm_from .. T-1, with a, b the walkers of copy 0 and 1
+ *      at slot k: the sites where they differ are ordered by (colour,
+ *      column, height) of the column layout (colour (x+y+z) mod 2, column
+ *      x/2 + (L/2) y, height z); if there are n > 0, the seed is number
+ *      floor(u n / 2^32), u = Philox word 0 of (k, t, 0xFFFFFFFE, run); the
+ *      cluster is every differing site connected to the seed through
+ *      differing sites and nonzero couplings; both walkers flip it (their
+ *      summed energy is unchanged, so the move is always taken);
+ *   3. inside each copy cp, ladder pairs (k, k+1), k = t mod 2, ... exchange
+ *      as in pt_run with u = Philox word 0 of (k + cp T, t, 0xFFFFFFFF, run).
+ * With icm_from >= T, copy 0 is exactly pt_run's chain. */
+#define SG_PTICM_MAX_T 32
+typedef struct sg_pticm_args {
+    int32_t n_runs;      /* >= 1 */
+    uint32_t run0;
+    int32_t T;           /* slots per copy, 2..SG_PTICM_MAX_T (2T walkers) */
+    int32_t n_steps;     /* >= 1 */
+    int32_t step0;       /* absolute index of the first step, >= 0 */
+    int32_t K;           /* row length of thr */
+    int32_t M;           /* row length of thrx, >= 1 */
+    int32_t init_random; /* 1: init-stream spins (replica word w) and pos[w] = w mod T */
+    int32_t icm_from;    /* first slot with cluster moves (>= T: none) */
+    int32_t reserved;
+    uint64_t seed;
+} sg_pticm_args;
+
+/* thr [T][K], thrx [T-1][M] as pt_run; spins [n_runs][2T][N], energy
+ * [n_runs][2T], pos [n_runs][2T] in/out; emin_trace [n_runs][n_steps]
+ * (minimum over the 2T walkers after each step), swap_acc [n_runs][2(T-1)]
+ * (copy-major, added to) and icm_flipped [n_runs][n_steps] (sites flipped
+ * per walker by the step's cluster moves) are nullable.  L <= 16. */
+int sg_pticm_run(const sg_instance *inst, const sg_pticm_args *args, const uint32_t *thr,
+                 const uint32_t *thrx, int8_t *spins, int32_t *energy, int32_t *pos,
+                 int32_t *emin_trace, uint32_t *swap_acc, int32_t *icm_flipped, void *stream);
+
 /* ---- the linear-time meta-heuristic (Sec. I) with simulated annealing as the
  * subsystem optimiser, bootstrapped over overlapping fragments (App. C) ----
  * The lattice is tiled by cores of c^3 spins (L % c == 0, nb = L/c per axis,

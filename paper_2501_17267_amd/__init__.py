@@ -52,6 +52,13 @@ class sg_sa_job(ctypes.Structure):
                 ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("emin", ctypes.c_void_p)]
 
 
+class sg_pticm_args(ctypes.Structure):
+    _fields_ = [("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32), ("T", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("step0", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("init_random", ctypes.c_int32), ("icm_from", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class sg_frag_args(ctypes.Structure):
     _fields_ = [("core", ctypes.c_int32), ("halo", ctypes.c_int32), ("replicas", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
@@ -123,6 +130,8 @@ def lib() -> ctypes.CDLL:
     L.sa_anneal.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp, vp]
     L.pt_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), vp, vp, vp, vp, vp, vp, vp, vp]
     L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
+    L.sg_pticm_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pticm_args), vp, vp, vp, vp, vp, vp, vp,
+                               vp, vp]
     L.sg_fragment_decimate.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_frag_args), vp, vp, vp, vp]
     L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
     L.sg_batch_create.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
@@ -140,7 +149,7 @@ def lib() -> ctypes.CDLL:
                "sg_sa_anneal_variant", "sg_autotune_sa", "sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
-               "sg_fragment_decimate",
+               "sg_fragment_decimate", "sg_pticm_run",
                "pt_run", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
@@ -342,6 +351,35 @@ def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0
                         _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
                         _stream(stream)), "pt_run")
     return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+
+
+def pticm_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, icm_from: int = 0,
+              run0: int = 0, step0: int = 0, spins=None, pos=None, want_trace: bool = False,
+              want_swaps: bool = False, want_icm: bool = False, stream=None):
+    """Parallel tempering with isoenergetic cluster moves: two copies of the
+    T-slot ladder thr (device [T][K]).  Returns dict(spins [n_runs][2T][N],
+    energy [n_runs][2T], pos, emin_trace, swap_acc, icm_flipped)."""
+    import torch
+    dev = inst.J.device
+    N = inst.L ** 3
+    T, K = int(thr.shape[0]), int(thr.shape[1])
+    M = int(thrx.shape[1])
+    W = 2 * T
+    init_random = spins is None
+    sp = torch.empty((n_runs, W, N), dtype=torch.int8, device=dev) if init_random else spins
+    ps = torch.empty((n_runs, W), dtype=torch.int32, device=dev) if init_random else pos
+    en = torch.empty((n_runs, W), dtype=torch.int32, device=dev)
+    tr = torch.empty((n_runs, n_steps), dtype=torch.int32, device=dev) if want_trace else None
+    sw = torch.zeros((n_runs, 2 * (T - 1)), dtype=torch.int32, device=dev) if want_swaps else None
+    ic = torch.empty((n_runs, n_steps), dtype=torch.int32, device=dev) if want_icm else None
+    args = sg_pticm_args(n_runs=n_runs, run0=run0, T=T, n_steps=n_steps, step0=step0, K=K, M=M,
+                         init_random=1 if init_random else 0, icm_from=icm_from,
+                         seed=seed & 0xFFFFFFFFFFFFFFFF)
+    _check(lib().sg_pticm_run(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                              _dptr(thrx, "thrx"), _dptr(sp, "spins"), _dptr(en, "energy"), _dptr(ps, "pos"),
+                              _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"), _dptr(ic, "icm_flipped"),
+                              _stream(stream)), "sg_pticm_run")
+    return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw, "icm_flipped": ic}
 
 
 def sa_variants(L: int) -> list[dict]:

@@ -1,0 +1,350 @@
+// pticm.hip -- parallel tempering with isoenergetic cluster moves (App. D,
+// PT+ICM; the cluster move is Houdayer's two-replica move as combined with
+// PT by Zhu, Ochoa and Katzgraber) and its C-ABI entry point.
+//
+// One work group runs one run: two copies of a T-slot ladder (2T walkers),
+// all LDS-resident in the colour-split column layout.  A step is the sweep
+// of every walker, then for every slot k >= icm_from one cluster move
+// between the two walkers at slot k, then the even/odd exchanges inside
+// each copy.  A cluster move works on byte masks in the same layout as the
+// spins: the disagreement mask is the XOR of the two walkers, a block-wide
+// prefix count picks the seed, and the cluster grows by repeated expansion
+// through neighbouring disagreeing sites joined by nonzero couplings (the
+// same byte shuffles as the local fields) until a pass adds nothing; both
+// walkers then XOR the cluster in.
+#include <algorithm>
+
+#include "common.hpp"
+#include "sweep.hpp"
+#include "variants.hpp"
+
+namespace sg {
+
+struct PtIcmJob {
+    const int8_t *J;
+    const uint32_t *jenc;
+    const uint32_t *thr;    // [T][K]
+    const uint32_t *thrx;   // [T-1][M]
+    int8_t *spins;          // [n_runs][2T][N]
+    int32_t *energy;        // [n_runs][2T]
+    int32_t *pos;           // [n_runs][2T]
+    int32_t *emin_trace;    // [n_runs][n_steps] or NULL
+    uint32_t *swap_acc;     // [n_runs][2(T-1)] or NULL
+    int32_t *icm_flipped;   // [n_runs][n_steps] or NULL
+    uint32_t run0;
+    int32_t T, n_steps, step0, K, M, icm_from, init_random;
+};
+
+constexpr int kIcmNW = 16;          // 1024 lanes: one dword of a walker per lane (L <= 16)
+constexpr int kIcmThr = kThrEntries;
+
+template <int L, bool JF>
+constexpr size_t pticm_lds_bytes(int T)
+{
+    using G = Geo<L>;
+    const size_t W = 2 * static_cast<size_t>(T);
+    return (W * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) + static_cast<size_t>(T) * kIcmThr + 3 * W +
+            2 * (static_cast<size_t>(T) - 1) + 2 * G::SPIN_DW + 64) * 4;
+}
+
+template <int L, bool JF>
+__global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0, uint32_t k1)
+{
+    using G = Geo<L>;
+    using Col = Column<L, JF>;
+    constexpr int NT = kIcmNW * 64;
+    constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
+    constexpr int SDW = G::SPIN_DW;
+    static_assert(SDW <= NT, "one dword of a walker per lane");
+    extern __shared__ uint32_t lds[];
+    const int T = job.T, W = 2 * T;
+    uint32_t *s_spin = lds;                                  // [W][SDW]
+    uint32_t *s_j = s_spin + W * SDW;
+    uint32_t *s_thr = s_j + JDW;                             // [T][64]
+    int32_t *s_E = reinterpret_cast<int32_t *>(s_thr + T * kIcmThr);
+    int32_t *s_pos = s_E + W;
+    int32_t *s_who = s_pos + W;                              // [copy * T + slot]
+    int32_t *s_sw = s_who + W;                               // [copy * (T-1) + k]
+    uint32_t *s_q = reinterpret_cast<uint32_t *>(s_sw + 2 * (T - 1));   // disagreement mask [SDW]
+    uint32_t *s_cl = s_q + SDW;                              // cluster mask [SDW]
+    int32_t *s_misc = reinterpret_cast<int32_t *>(s_cl + SDW);   // 64 words: scan totals, seed, flags
+
+    const int tid = static_cast<int>(threadIdx.x);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int run = static_cast<int>(blockIdx.x);
+    const uint32_t chain = job.run0 + static_cast<uint32_t>(run);
+    int8_t *spins = job.spins + static_cast<int64_t>(run) * W * G::N;
+
+    // ---- set-up ---------------------------------------------------------
+    for (int w = tid; w < W * SDW; w += NT) s_spin[w] = 0u;
+    for (int w = tid; w < T * kIcmThr; w += NT) {
+        const int slot = w / kIcmThr, e = w - slot * kIcmThr;
+        s_thr[w] = thr_entry(job.thr + slot * job.K, job.K, e);
+    }
+    if (tid < W) {
+        s_E[tid] = 0;
+        int p = job.init_random ? tid % T : job.pos[run * W + tid];
+        if (p < 0 || p >= T) p = tid % T;  // keeps LDS indices in range; pos must be a permutation per copy
+        s_pos[tid] = p;
+    }
+    if (tid < 2 * (T - 1)) s_sw[tid] = 0;
+    load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
+    __syncthreads();
+    if (tid < W) s_who[(tid / T) * T + s_pos[tid]] = tid;
+    {
+        uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
+        constexpr int Q = G::N / 4;
+        for (int w = tid; w < W * Q; w += NT) {
+            const int wk = w / Q;
+            const int q = w - wk * Q;
+            load_spins_one<L>(sb + wk * SDW * 4, q, job.init_random != 0, spins + static_cast<int64_t>(wk) * G::N,
+                              static_cast<uint32_t>(wk), chain, k0, k1);
+        }
+    }
+    __syncthreads();
+    for (int u = tid; u < W * G::NC; u += NT) {
+        const int wk = u / G::NC;
+        atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * SDW, s_j, u - wk * G::NC));
+    }
+    __syncthreads();
+
+    // lane tid owns dword tid of a walker's column-major array: (c, col, m)
+    const bool own = tid < SDW;
+    const int oc_c = tid / (G::NC * G::C);
+    const int oc_col = (tid / G::C) % G::NC;
+    const int oc_m = tid % G::C;
+
+    for (int ti = 0; ti < job.n_steps; ++ti) {
+        const uint32_t t = static_cast<uint32_t>(job.step0 + ti);
+        // ---- 1. sweeps ----------------------------------------------------------
+        for (int c = 0; c < 2; ++c) {
+            for (int u = tid; u < W * G::NC; u += NT) {
+                const int wk = u / G::NC;
+                const int col = u - wk * G::NC;
+                const int32_t dE = Col::template metropolis<true>(
+                    s_spin + wk * SDW, s_j, s_thr + s_pos[wk] * kIcmThr, c, col, 2u * t + static_cast<uint32_t>(c),
+                    static_cast<uint32_t>(wk), chain, k0, k1);
+                if (dE != 0) atomicAdd(&s_E[wk], dE);
+            }
+            __syncthreads();
+        }
+        // ---- 2. cluster moves, slot by slot --------------------------------------
+        int32_t flipped = 0;
+        for (int k = job.icm_from; k < T; ++k) {
+            const int a = s_who[k], b = s_who[T + k];
+            uint32_t *sa = s_spin + a * SDW, *sbp = s_spin + b * SDW;
+            // disagreement mask and its block-wide prefix count (dword order =
+            // (colour, column, height))
+            const uint32_t q = own ? (sa[tid] ^ sbp[tid]) : 0u;
+            if (own) {
+                s_q[tid] = q;
+                s_cl[tid] = 0u;
+            }
+            const int cnt = __popc(q) >> 3;
+            int incl = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            if (lane == 63) s_misc[wave] = incl;
+            __syncthreads();
+            if (tid == 0) {
+                int acc = 0;
+                for (int w = 0; w < kIcmNW; ++w) {
+                    const int v = s_misc[w];
+                    s_misc[w] = acc;
+                    acc += v;
+                }
+                s_misc[kIcmNW] = acc;        // n: disagreeing sites
+                s_misc[kIcmNW + 1] = -1;     // seed byte index
+            }
+            __syncthreads();
+            const int n = s_misc[kIcmNW];
+            if (n == 0) continue;            // uniform: every lane sees the same n
+            const Rand4 uu = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFEu, chain, k0, k1);
+            const int idx = static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
+            const int excl = s_misc[wave] + incl - cnt;
+            if (own && idx >= excl && idx < excl + cnt) {
+                int r = idx - excl, b2 = 0;
+                for (; b2 < 4; ++b2)
+                    if ((q >> (8 * b2)) & 0xFFu) {
+                        if (r == 0) break;
+                        --r;
+                    }
+                s_misc[kIcmNW + 1] = tid * 4 + b2;
+            }
+            __syncthreads();
+            const int seed = s_misc[kIcmNW + 1];
+            if (tid == seed >> 2) s_cl[tid] = 0xFFu << (8 * (seed & 3));
+            __syncthreads();
+            // growth until a pass adds nothing
+            int grown = 1;
+            while (grown) {
+                int add = 0;
+                if (own) {
+                    uint32_t nb[6];
+                    Col::nbr_dwords(s_cl, oc_c, oc_col, oc_m, nb);
+                    uint32_t reach = 0;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) reach |= nb[d] & Col::nonzero_coupling(s_j, oc_c, oc_col, d, oc_m);
+                    const uint32_t cur = s_cl[tid];
+                    const uint32_t nw = reach & s_q[tid] & ~cur;
+                    if (nw) {
+                        s_cl[tid] = cur | nw;
+                        add = 1;
+                    }
+                }
+                grown = __syncthreads_or(add);
+            }
+            // flip the cluster in both walkers; their energies again
+            if (own) {
+                const uint32_t cl = s_cl[tid];
+                sa[tid] ^= cl;
+                sbp[tid] ^= cl;
+            }
+            if (tid == 0) {
+                s_E[a] = 0;
+                s_E[b] = 0;
+            }
+            int ccount = own ? (__popc(s_cl[tid]) >> 3) : 0;
+            for (int off = 32; off > 0; off >>= 1) ccount += __shfl_xor(ccount, off, 64);
+            if (lane == 0) s_misc[32 + wave] = ccount;
+            __syncthreads();
+            for (int u = tid; u < 2 * G::NC; u += NT) {
+                const int which = u / G::NC;
+                const int wk = which ? b : a;
+                atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * SDW, s_j, u - which * G::NC));
+            }
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < kIcmNW; ++w) tot += s_misc[32 + w];
+                s_misc[kIcmNW + 2] = tot;
+            }
+            __syncthreads();
+            flipped += s_misc[kIcmNW + 2];
+        }
+        // ---- 3. exchanges inside each copy ---------------------------------------
+        if (tid < 2 * T) {
+            const int cp = tid / T, k = tid - cp * T;
+            if (k + 1 < T && ((k ^ static_cast<int>(t)) & 1) == 0) {
+                const int a = s_who[cp * T + k], b = s_who[cp * T + k + 1];
+                const int32_t D = s_E[a] - s_E[b];
+                bool acc = D <= 0;
+                if (!acc) {
+                    const int32_t m = D / 2;
+                    const Rand4 u = philox10(static_cast<uint32_t>(k + cp * T), t, 0xFFFFFFFFu, chain, k0, k1);
+                    acc = (m <= job.M) && (u.w[0] < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
+                }
+                if (acc) {
+                    s_who[cp * T + k] = b;
+                    s_who[cp * T + k + 1] = a;
+                    s_pos[b] = k;
+                    s_pos[a] = k + 1;
+                    s_sw[cp * (T - 1) + k] += 1;
+                }
+            }
+        }
+        if (tid >= 64 && tid < 128) {
+            int32_t e = 0x7FFFFFFF;
+            for (int w = lane; w < W; w += 64) e = min(e, s_E[w]);
+            for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
+            if (lane == 0) {
+                if (job.emin_trace) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = e;
+                if (job.icm_flipped) job.icm_flipped[static_cast<int64_t>(run) * job.n_steps + ti] = flipped;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write-back ---------------------------------------------------------
+    {
+        const uint8_t *sb = reinterpret_cast<const uint8_t *>(s_spin);
+        constexpr int Q = G::N / 4;
+        for (int w = tid; w < W * Q; w += NT) {
+            const int wk = w / Q;
+            const int q = w - wk * Q;
+            store_spins_one<L>(sb + wk * SDW * 4, q, spins + static_cast<int64_t>(wk) * G::N);
+        }
+    }
+    if (tid < W) {
+        job.energy[run * W + tid] = s_E[tid];
+        job.pos[run * W + tid] = s_pos[tid];
+    }
+    if (job.swap_acc && tid < 2 * (T - 1)) job.swap_acc[run * 2 * (T - 1) + tid] += static_cast<uint32_t>(s_sw[tid]);
+}
+
+template <int L>
+static int launch_pticm(const PtIcmJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+{
+    constexpr bool JF = (L <= 12);
+    const size_t bytes = pticm_lds_bytes<L, JF>(job.T);
+    if (bytes > 160 * 1024)
+        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
+    auto kern = k_pticm<L, JF>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+    if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: LDS attribute: %s", hipGetErrorString(err));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, job, k0, k1);
+    err = hipGetLastError();
+    if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: launch failed: %s", hipGetErrorString(err));
+    return SG_OK;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" int sg_pticm_run(const sg_instance *inst, const sg_pticm_args *args, const uint32_t *thr,
+                            const uint32_t *thrx, int8_t *spins, int32_t *energy_out, int32_t *pos,
+                            int32_t *emin_trace, uint32_t *swap_acc, int32_t *icm_flipped, void *stream)
+{
+    if (!inst || !args) return fail(SG_EINVAL, "sg_pticm_run: NULL instance or args");
+    if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "sg_pticm_run: L = %d must be even in [4, %d]", inst->L, SG_MAX_L);
+    if (!inst->J && !inst->jenc) return fail(SG_EINVAL, "sg_pticm_run: instance has no couplings");
+    if (!thr || !thrx || !spins || !energy_out || !pos) return fail(SG_EINVAL, "sg_pticm_run: NULL array");
+    if (args->n_runs < 1 || args->n_steps < 1)
+        return fail(SG_EINVAL, "sg_pticm_run: n_runs = %d, n_steps = %d", args->n_runs, args->n_steps);
+    if (args->T < 2 || args->T > SG_PTICM_MAX_T)
+        return fail(SG_EINVAL, "sg_pticm_run: T = %d outside [2, %d]", args->T, SG_PTICM_MAX_T);
+    if (args->K < 1 || args->K > SG_K_MAX || args->M < 1)
+        return fail(SG_EINVAL, "sg_pticm_run: K = %d, M = %d", args->K, args->M);
+    if (args->icm_from < 0) return fail(SG_EINVAL, "sg_pticm_run: icm_from = %d", args->icm_from);
+    if (args->step0 < 0 || static_cast<int64_t>(args->step0) + args->n_steps > (1 << 30))
+        return fail(SG_ERANGE, "sg_pticm_run: steps must stay below 2^30");
+    if (static_cast<uint64_t>(args->run0) + static_cast<uint64_t>(args->n_runs) > 0xFFFFFFFFull)
+        return fail(SG_ERANGE, "sg_pticm_run: run counter words overflow");
+    if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0) return fail(SG_EINVAL, "sg_pticm_run: spins must be 4-byte aligned");
+    PtIcmJob job{};
+    job.J = inst->J;
+    job.jenc = inst->jenc;
+    job.thr = thr;
+    job.thrx = thrx;
+    job.spins = spins;
+    job.energy = energy_out;
+    job.pos = pos;
+    job.emin_trace = emin_trace;
+    job.swap_acc = swap_acc;
+    job.icm_flipped = icm_flipped;
+    job.run0 = args->run0;
+    job.T = args->T;
+    job.n_steps = args->n_steps;
+    job.step0 = args->step0;
+    job.K = args->K;
+    job.M = args->M;
+    job.icm_from = args->icm_from;
+    job.init_random = args->init_random ? 1 : 0;
+    clear_error();
+    const uint32_t k0 = static_cast<uint32_t>(args->seed), k1 = static_cast<uint32_t>(args->seed >> 32);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (inst->L) {
+    case 4: return launch_pticm<4>(job, args->n_runs, k0, k1, st);
+    case 6: return launch_pticm<6>(job, args->n_runs, k0, k1, st);
+    case 8: return launch_pticm<8>(job, args->n_runs, k0, k1, st);
+    case 10: return launch_pticm<10>(job, args->n_runs, k0, k1, st);
+    case 12: return launch_pticm<12>(job, args->n_runs, k0, k1, st);
+    case 14: return launch_pticm<14>(job, args->n_runs, k0, k1, st);
+    case 16: return launch_pticm<16>(job, args->n_runs, k0, k1, st);
+    default: return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d is above the LDS-resident range", inst->L);
+    }
+}

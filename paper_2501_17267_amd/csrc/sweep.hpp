@@ -151,11 +151,11 @@ struct Column {
         }
     }
 
-    // Kb of dword m only, loading just what it needs (the streaming path for
-    // long columns, where six whole neighbour columns would not fit in
-    // registers)
-    __device__ static uint32_t field_dword(const uint32_t *rep, const uint32_t *jl, int c, int col, int m,
-                                           uint32_t own_m)
+    // The six neighbour bytes (+x, -x, +y, -y, +z, -z) of the four sites of
+    // dword m of colour-c column col, gathered from the colour-(1-c)
+    // columns of a byte array in the column layout (spins, or any per-site
+    // byte mask laid out the same way)
+    __device__ static void nbr_dwords(const uint32_t *rep, int c, int col, int m, uint32_t (&nb)[6])
     {
         const Nbr n = neighbours(c, col);
         const int oc = c ^ 1;
@@ -169,10 +169,32 @@ struct Column {
             zm = __builtin_amdgcn_perm(s_m, rep[spin_at<L, SLAY>(oc, n.self, C - 1)], 0x06050401u);
         else
             zm = __builtin_amdgcn_alignbyte(s_m, rep[spin_at<L, SLAY>(oc, n.self, m > 0 ? m - 1 : C - 1)], 3);
-        const uint32_t nb[6] = {bfi(n.even_x, s_m, rep[spin_at<L, SLAY>(oc, n.xp, m)]),
-                                bfi(n.even_x, rep[spin_at<L, SLAY>(oc, n.xm, m)], s_m),
-                                rep[spin_at<L, SLAY>(oc, n.yp, m)], rep[spin_at<L, SLAY>(oc, n.ym, m)], zp, zm};
+        nb[0] = bfi(n.even_x, s_m, rep[spin_at<L, SLAY>(oc, n.xp, m)]);
+        nb[1] = bfi(n.even_x, rep[spin_at<L, SLAY>(oc, n.xm, m)], s_m);
+        nb[2] = rep[spin_at<L, SLAY>(oc, n.yp, m)];
+        nb[3] = rep[spin_at<L, SLAY>(oc, n.ym, m)];
+        nb[4] = zp;
+        nb[5] = zm;
+    }
+
+    // Kb of dword m only, loading just what it needs (the streaming path for
+    // long columns, where six whole neighbour columns would not fit in
+    // registers)
+    __device__ static uint32_t field_dword(const uint32_t *rep, const uint32_t *jl, int c, int col, int m,
+                                           uint32_t own_m)
+    {
+        uint32_t nb[6];
+        nbr_dwords(rep, c, col, m, nb);
         return field_to_kb(own_m, field_sum(jl, c, col, m, nb));
+    }
+
+    // 0xFF in every byte of dword m of colour-c column col whose coupling in
+    // direction d is nonzero (E = J + 8 differs from 8)
+    __device__ static uint32_t nonzero_coupling(const uint32_t *jl, int c, int col, int d, int m)
+    {
+        const uint32_t x = jl[coupling_at<L, HN, JLAY>(c, col, d, 0, m)] ^ 0x08080808u;  // J & 15 per byte
+        const uint32_t t = ((x & 0x0F0F0F0Fu) + 0x0F0F0F0Fu) & 0x10101010u;             // bit 4: J != 0
+        return (t >> 4) * 0xFFu;
     }
 
     // columns longer than this are processed dword by dword

@@ -14,9 +14,10 @@ pt_ladder_grid PT ladders (T walkers, geometric 0.2 -> beta_max) at L = 6:
                the steps at which the mean over 20 runs of the best energy
                seen so far reaches the target, per instance; the ladder with
                the least work (steps x T sweeps) wins.
-pt_tteps       PT TT-eps versus N (L = 6, 8, 10, 12) at eps = 3, 4, 5 % with
-               the chosen ladder: per instance one pt_run of 20 runs with the
-               per-step minimum-energy trace; TT-eps = the time of the steps
+pt_tteps       PT (and PT with isoenergetic cluster moves) TT-eps versus N
+               (L = 6, 8, 10, 12) at eps = 3, 4, 5 % with the chosen ladder:
+               per instance one launch of 20 runs with the per-step
+               minimum-energy trace; TT-eps = the time of the steps
                needed, from the measured time per step of one run alone
                (plain) and of the 20-run launch divided by 20 (batched).
 """
@@ -27,7 +28,7 @@ import time
 import numpy as np
 
 from . import (Batch, Instance, SAJob, epsilon, exchange_table_width, make_exchange_thresholds, make_schedule,
-               make_thresholds, pt_run, to_device_u32)
+               make_thresholds, pt_run, pticm_run, to_device_u32)
 from . import workloads as wl
 from .tteps import _fit, sweep_grid
 
@@ -72,11 +73,18 @@ def _pt_tables(T, beta_max):
     return to_device_u32(make_thresholds(beta)), to_device_u32(make_exchange_thresholds(beta, M))
 
 
-def _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, targets):
+def _pt_call(inst, thr, thrx, n_runs, n_steps, seed, icm_from=None, want_trace=False):
+    """PT (icm_from None) or PT with cluster moves from slot icm_from."""
+    if icm_from is None:
+        return pt_run(inst, thr, thrx, n_runs, n_steps, seed, want_trace=want_trace)
+    return pticm_run(inst, thr, thrx, n_runs, n_steps, seed, icm_from=icm_from, want_trace=want_trace)
+
+
+def _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, targets, icm_from=None):
     """Run n_runs runs of n_steps; return ({target: steps or None}, ms of the call)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = pt_run(inst, thr, thrx, n_runs, n_steps, seed, want_trace=True)
+    out = _pt_call(inst, thr, thrx, n_runs, n_steps, seed, icm_from, want_trace=True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     tr = out["emin_trace"].cpu().numpy().astype(np.int64)
@@ -90,7 +98,9 @@ def _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, targets)
 
 
 def pt_ladder_grid(torch, L=6, n_inst=20, n_runs=20, target=0.03, n_steps=2000,
-                   Ts=(8, 16, 32), beta_maxs=(2.0, 3.0, 5.0), log=print):
+                   Ts=(8, 16, 32), beta_maxs=(2.0, 3.0, 5.0), icm=False, log=print):
+    """With icm, each ladder is tried with cluster moves on every slot and on
+    the colder half (icm_from = 0, T/2); the work counts both copies."""
     seed = wl.philox_seed("pt") ^ 0x3C
     specs = [wl.InstanceSpec(L, wl.instance_seed("pt", 100 + k), k) for k in range(n_inst)]
     insts = [Instance.generate(s.L, s.seed, s.chain) for s in specs]
@@ -98,24 +108,27 @@ def pt_ladder_grid(torch, L=6, n_inst=20, n_runs=20, target=0.03, n_steps=2000,
     for T in Ts:
         for bm in beta_maxs:
             thr, thrx = _pt_tables(T, bm)
-            steps = []
-            for inst in insts:
-                r, _ = _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, (target,))
-                steps.append(r[target])
-            ok = all(x is not None for x in steps)
-            row = {"T": T, "beta_max": bm, "censored": not ok,
-                   "mean_steps": float(np.mean(steps)) if ok else None,
-                   "mean_sweeps": float(np.mean(steps)) * T if ok else None,
-                   "reached": int(sum(x is not None for x in steps))}
-            log(f"pt grid {row}")
-            rows.append(row)
+            for icm_from in ((0, T // 2) if icm else (None,)):
+                steps = []
+                for inst in insts:
+                    r, _ = _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, (target,), icm_from)
+                    steps.append(r[target])
+                ok = all(x is not None for x in steps)
+                walkers = T * (2 if icm else 1)
+                row = {"T": T, "beta_max": bm, "icm_from": icm_from, "censored": not ok,
+                       "mean_steps": float(np.mean(steps)) if ok else None,
+                       "mean_sweeps": float(np.mean(steps)) * walkers if ok else None,
+                       "reached": int(sum(x is not None for x in steps))}
+                log(f"pt{'+icm' if icm else ''} grid {row}")
+                rows.append(row)
     done = [r for r in rows if not r["censored"]]
     best = min(done, key=lambda r: r["mean_sweeps"]) if done else None
     return {"L": L, "target": target, "rows": rows, "best": best}
 
 
 def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=20,
-             targets=(0.03, 0.04, 0.05), n_steps=4000, log=print):
+             targets=(0.03, 0.04, 0.05), n_steps=4000, icm_from=None, log=print):
+    """icm_from None: PT; else PT with cluster moves from that slot."""
     seed = wl.philox_seed("pt") ^ 0x71
     thr, thrx = _pt_tables(T, beta_max)
     per_L = {}
@@ -123,16 +136,16 @@ def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=
         specs = [wl.InstanceSpec(L, wl.instance_seed("pt", 1000 * L + k), k) for k in range(n_inst)]
         insts = [Instance.generate(s.L, s.seed, s.chain) for s in specs]
         # time per step of one run alone and of the n_runs launch
-        pt_run(insts[0], thr, thrx, 1, 50, seed)
+        _pt_call(insts[0], thr, thrx, 1, 50, seed, icm_from)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pt_run(insts[0], thr, thrx, 1, n_steps, seed)
+        _pt_call(insts[0], thr, thrx, 1, n_steps, seed, icm_from)
         torch.cuda.synchronize()
         ms_step_plain = (time.perf_counter() - t0) * 1e3 / n_steps
         steps = {t: [] for t in targets}
         batch_ms = []
         for inst in insts:
-            r, ms = _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, targets)
+            r, ms = _pt_steps_to_targets(torch, inst, thr, thrx, n_runs, n_steps, seed, targets, icm_from)
             batch_ms.append(ms)
             for t in targets:
                 steps[t].append(r[t])
@@ -147,14 +160,15 @@ def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=
             entry["targets"][str(t)] = {"censored": False, "steps_mean": float(np.mean(st)),
                                         "plain_ms": float(np.mean(st)) * ms_step_plain,
                                         "batched_ms": float(np.mean(st)) * ms_step_batched}
-        log(f"pt tteps L={L}: {entry}")
+        log(f"pt{'' if icm_from is None else '+icm'} tteps L={L}: {entry}")
         per_L[L] = entry
     fits = {}
     for t in targets:
         pts = [(v["N"], v["targets"][str(t)]) for v in per_L.values() if not v["targets"][str(t)]["censored"]]
         fits[str(t)] = {form: _fit([N for N, _ in pts], [e[key] for _, e in pts])
                         for form, key in (("plain", "plain_ms"), ("batched", "batched_ms"))}
-    return {"T": T, "beta_max": beta_max, "per_L": {str(L): v for L, v in per_L.items()}, "fits": fits}
+    return {"T": T, "beta_max": beta_max, "icm_from": icm_from, "per_L": {str(L): v for L, v in per_L.items()},
+            "fits": fits}
 
 
 def run(torch, log=print):
@@ -169,4 +183,9 @@ def run(torch, log=print):
                                  served=False, log=log, schedule=(b["kind"], b["beta0"], b["beta1"]))
     if pt["best"]:
         out["pt_alpha"] = pt_tteps(torch, T=pt["best"]["T"], beta_max=pt["best"]["beta_max"], log=log)
+    icm = pt_ladder_grid(torch, Ts=(4, 8, 16), beta_maxs=(2.0, 3.0), icm=True, log=log)
+    out["pticm_grid"] = icm
+    if icm["best"]:
+        b = icm["best"]
+        out["pticm_alpha"] = pt_tteps(torch, T=b["T"], beta_max=b["beta_max"], icm_from=b["icm_from"], log=log)
     return out
