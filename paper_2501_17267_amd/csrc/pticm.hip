@@ -33,18 +33,21 @@ struct PtIcmJob {
     int32_t *icm_flipped;   // [n_runs][n_steps] or NULL
     uint32_t run0;
     int32_t T, n_steps, step0, K, M, icm_from, init_random;
+    int32_t G;              // slots whose cluster moves run together
 };
 
-constexpr int kIcmNW = 16;          // 1024 lanes: one dword of a walker per lane (L <= 16)
+constexpr int kIcmNW = 16;          // 1024 lanes per run
 constexpr int kIcmThr = kThrEntries;
 
+// LDS of one run with cluster moves of ng slots at once
 template <int L, bool JF>
-constexpr size_t pticm_lds_bytes(int T)
+constexpr size_t pticm_lds_bytes(int T, int ng)
 {
     using G = Geo<L>;
     const size_t W = 2 * static_cast<size_t>(T);
     return (W * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) + static_cast<size_t>(T) * kIcmThr + 3 * W +
-            2 * (static_cast<size_t>(T) - 1) + 2 * G::SPIN_DW + 64) * 4;
+            2 * (static_cast<size_t>(T) - 1) + 2 * static_cast<size_t>(ng) * G::SPIN_DW + 64 +
+            2 * static_cast<size_t>(T)) * 4;
 }
 
 template <int L, bool JF>
@@ -55,7 +58,6 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     constexpr int NT = kIcmNW * 64;
     constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
     constexpr int SDW = G::SPIN_DW;
-    static_assert(SDW <= NT, "one dword of a walker per lane");
     extern __shared__ uint32_t lds[];
     const int T = job.T, W = 2 * T;
     uint32_t *s_spin = lds;                                  // [W][SDW]
@@ -65,9 +67,11 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     int32_t *s_pos = s_E + W;
     int32_t *s_who = s_pos + W;                              // [copy * T + slot]
     int32_t *s_sw = s_who + W;                               // [copy * (T-1) + k]
-    uint32_t *s_q = reinterpret_cast<uint32_t *>(s_sw + 2 * (T - 1));   // disagreement mask [SDW]
-    uint32_t *s_cl = s_q + SDW;                              // cluster mask [SDW]
-    int32_t *s_misc = reinterpret_cast<int32_t *>(s_cl + SDW);   // 64 words: scan totals, seed, flags
+    uint32_t *s_q = reinterpret_cast<uint32_t *>(s_sw + 2 * (T - 1));   // disagreement masks [G][SDW]
+    uint32_t *s_cl = s_q + job.G * SDW;                      // cluster masks [G][SDW]
+    int32_t *s_misc = reinterpret_cast<int32_t *>(s_cl + job.G * SDW);   // 64 words: scan, flip counts
+    int32_t *s_n = s_misc + 64;                              // [G] disagreeing sites per slot
+    int32_t *s_tgt = s_n + T;                                // [G] seed position per slot
 
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = tid & 63, wave = tid >> 6;
@@ -108,12 +112,6 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     }
     __syncthreads();
 
-    // lane tid owns dword tid of a walker's column-major array: (c, col, m)
-    const bool own = tid < SDW;
-    const int oc_c = tid / (G::NC * G::C);
-    const int oc_col = (tid / G::C) % G::NC;
-    const int oc_m = tid % G::C;
-
     for (int ti = 0; ti < job.n_steps; ++ti) {
         const uint32_t t = static_cast<uint32_t>(job.step0 + ti);
         // ---- 1. sweeps ----------------------------------------------------------
@@ -128,20 +126,30 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
             }
             __syncthreads();
         }
-        // ---- 2. cluster moves, slot by slot --------------------------------------
+        // ---- 2. cluster moves: the slots icm_from.. in groups of G at once -------
+        // (the slots' walker pairs are disjoint, so the moves are independent).
+        // Element p = g * SDW + w is dword w of slot k0s + g; each lane owns a
+        // contiguous range of elements, so a block scan over the lanes orders
+        // the disagreeing sites slot by slot, then by (colour, column, height).
         int32_t flipped = 0;
-        for (int k = job.icm_from; k < T; ++k) {
-            const int a = s_who[k], b = s_who[T + k];
-            uint32_t *sa = s_spin + a * SDW, *sbp = s_spin + b * SDW;
-            // disagreement mask and its block-wide prefix count (dword order =
-            // (colour, column, height))
-            const uint32_t q = own ? (sa[tid] ^ sbp[tid]) : 0u;
-            if (own) {
-                s_q[tid] = q;
-                s_cl[tid] = 0u;
+        for (int k0s = job.icm_from; k0s < T; k0s += job.G) {
+            const int gn = min(job.G, T - k0s);
+            const int tot = gn * SDW;
+            const int per = (tot + NT - 1) / NT;
+            const int p0 = min(tid * per, tot), p1 = min(p0 + per, tot);
+            if (tid < gn) s_n[tid] = 0;
+            __syncthreads();
+            int lsum = 0;
+            for (int p = p0; p < p1; ++p) {
+                const int g = p / SDW, w = p - g * SDW;
+                const uint32_t q = s_spin[s_who[k0s + g] * SDW + w] ^ s_spin[s_who[T + k0s + g] * SDW + w];
+                s_q[p] = q;
+                s_cl[p] = 0u;
+                const int cnt = __popc(q) >> 3;
+                if (cnt) atomicAdd(&s_n[g], cnt);
+                lsum += cnt;
             }
-            const int cnt = __popc(q) >> 3;
-            int incl = cnt;
+            int incl = lsum;
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(incl, off, 64);
                 if (lane >= off) incl += v;
@@ -155,73 +163,96 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
                     s_misc[w] = acc;
                     acc += v;
                 }
-                s_misc[kIcmNW] = acc;        // n: disagreeing sites
-                s_misc[kIcmNW + 1] = -1;     // seed byte index
+            }
+            if (tid < gn) {
+                // seed of slot k0s + tid: its position among all disagreeing
+                // sites of the group (-1: the two walkers agree everywhere)
+                int start = 0;
+                for (int g = 0; g < tid; ++g) start += s_n[g];
+                const int n = s_n[tid];
+                int tgt = -1;
+                if (n > 0) {
+                    const Rand4 uu = philox10(static_cast<uint32_t>(k0s + tid), t, 0xFFFFFFFEu, chain, k0, k1);
+                    tgt = start + static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
+                }
+                s_tgt[tid] = tgt;
             }
             __syncthreads();
-            const int n = s_misc[kIcmNW];
-            if (n == 0) continue;            // uniform: every lane sees the same n
-            const Rand4 uu = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFEu, chain, k0, k1);
-            const int idx = static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
-            const int excl = s_misc[wave] + incl - cnt;
-            if (own && idx >= excl && idx < excl + cnt) {
-                int r = idx - excl, b2 = 0;
-                for (; b2 < 4; ++b2)
-                    if ((q >> (8 * b2)) & 0xFFu) {
-                        if (r == 0) break;
-                        --r;
+            {
+                const int excl = s_misc[wave] + incl - lsum;
+                for (int g = 0; g < gn; ++g) {
+                    const int tgt = s_tgt[g];
+                    if (tgt < excl || tgt >= excl + lsum) continue;
+                    int r = tgt - excl;
+                    for (int p = p0; p < p1; ++p) {
+                        const uint32_t q = s_q[p];
+                        const int cnt = __popc(q) >> 3;
+                        if (r >= cnt) {
+                            r -= cnt;
+                            continue;
+                        }
+                        for (int b2 = 0; b2 < 4; ++b2)
+                            if ((q >> (8 * b2)) & 0xFFu) {
+                                if (r == 0) {
+                                    s_cl[p] = 0xFFu << (8 * b2);
+                                    break;
+                                }
+                                --r;
+                            }
+                        break;
                     }
-                s_misc[kIcmNW + 1] = tid * 4 + b2;
+                }
             }
             __syncthreads();
-            const int seed = s_misc[kIcmNW + 1];
-            if (tid == seed >> 2) s_cl[tid] = 0xFFu << (8 * (seed & 3));
-            __syncthreads();
-            // growth until a pass adds nothing
+            // growth of every slot's cluster until a pass adds nothing
             int grown = 1;
             while (grown) {
                 int add = 0;
-                if (own) {
+                for (int p = p0; p < p1; ++p) {
+                    const int g = p / SDW, w = p - g * SDW;
+                    const int c = w / (G::NC * G::C), col = (w / G::C) % G::NC, m = w % G::C;
                     uint32_t nb[6];
-                    Col::nbr_dwords(s_cl, oc_c, oc_col, oc_m, nb);
+                    Col::nbr_dwords(s_cl + g * SDW, c, col, m, nb);
                     uint32_t reach = 0;
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) reach |= nb[d] & Col::nonzero_coupling(s_j, oc_c, oc_col, d, oc_m);
-                    const uint32_t cur = s_cl[tid];
-                    const uint32_t nw = reach & s_q[tid] & ~cur;
+                    for (int d = 0; d < 6; ++d) reach |= nb[d] & Col::nonzero_coupling(s_j, c, col, d, m);
+                    const uint32_t cur = s_cl[p];
+                    const uint32_t nw = reach & s_q[p] & ~cur;
                     if (nw) {
-                        s_cl[tid] = cur | nw;
+                        s_cl[p] = cur | nw;
                         add = 1;
                     }
                 }
                 grown = __syncthreads_or(add);
             }
-            // flip the cluster in both walkers; their energies again
-            if (own) {
-                const uint32_t cl = s_cl[tid];
-                sa[tid] ^= cl;
-                sbp[tid] ^= cl;
+            // flip every cluster in both walkers of its slot
+            int fl = 0;
+            for (int p = p0; p < p1; ++p) {
+                const int g = p / SDW, w = p - g * SDW;
+                const uint32_t cl = s_cl[p];
+                if (!cl) continue;
+                s_spin[s_who[k0s + g] * SDW + w] ^= cl;
+                s_spin[s_who[T + k0s + g] * SDW + w] ^= cl;
+                fl += __popc(cl) >> 3;
             }
-            if (tid == 0) {
-                s_E[a] = 0;
-                s_E[b] = 0;
-            }
-            int ccount = own ? (__popc(s_cl[tid]) >> 3) : 0;
-            for (int off = 32; off > 0; off >>= 1) ccount += __shfl_xor(ccount, off, 64);
-            if (lane == 0) s_misc[32 + wave] = ccount;
+            for (int off = 32; off > 0; off >>= 1) fl += __shfl_xor(fl, off, 64);
+            if (lane == 0) s_misc[32 + wave] = fl;
+            if (tid < 2 * gn) s_E[s_who[(tid / gn) * T + k0s + tid % gn]] = 0;
             __syncthreads();
-            for (int u = tid; u < 2 * G::NC; u += NT) {
-                const int which = u / G::NC;
-                const int wk = which ? b : a;
-                atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * SDW, s_j, u - which * G::NC));
+            // energies of the moved walkers
+            for (int u = tid; u < 2 * gn * G::NC; u += NT) {
+                const int pw = u / G::NC;
+                const int wk = s_who[(pw / gn) * T + k0s + pw % gn];
+                atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * SDW, s_j, u - pw * G::NC));
             }
             if (tid == 0) {
-                int tot = 0;
-                for (int w = 0; w < kIcmNW; ++w) tot += s_misc[32 + w];
-                s_misc[kIcmNW + 2] = tot;
+                int tot_fl = 0;
+                for (int w = 0; w < kIcmNW; ++w) tot_fl += s_misc[32 + w];
+                s_misc[kIcmNW + 2] = tot_fl;
             }
             __syncthreads();
             flipped += s_misc[kIcmNW + 2];
+            __syncthreads();
         }
         // ---- 3. exchanges inside each copy ---------------------------------------
         if (tid < 2 * T) {
@@ -277,15 +308,22 @@ template <int L>
 static int launch_pticm(const PtIcmJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
     constexpr bool JF = (L <= 12);
-    const size_t bytes = pticm_lds_bytes<L, JF>(job.T);
-    if (bytes > 160 * 1024)
-        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
+    constexpr size_t kLds = 160 * 1024;
+    const size_t base = pticm_lds_bytes<L, JF>(job.T, 1);
+    if (base > kLds)
+        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, base);
+    // as many slots' cluster moves at once as the LDS left over holds
+    PtIcmJob jb = job;
+    const int slots = std::max(1, job.T - job.icm_from);
+    const size_t per_slot = 2 * static_cast<size_t>(Geo<L>::SPIN_DW) * 4;
+    jb.G = static_cast<int32_t>(std::min<size_t>(slots, 1 + (kLds - base) / per_slot));
+    const size_t bytes = pticm_lds_bytes<L, JF>(job.T, jb.G);
     auto kern = k_pticm<L, JF>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: LDS attribute: %s", hipGetErrorString(err));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, job, k0, k1);
+    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, jb, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: launch failed: %s", hipGetErrorString(err));
     return SG_OK;
