@@ -228,6 +228,56 @@ def fragment(a, sg, wl, torch):
     return res
 
 
+def wide(a, sg, wl, torch):
+    """One anneal of few replicas of L = 32 and 64 (256 sweeps): the
+    multi-work-group path that sa_anneal picks by itself, against the
+    single-work-group kernel of the same size; results are identical."""
+    out = {"metric": "ms per anneal of few replicas, wide path vs one work group per replica group", "rows": []}
+    thr = sg.to_device_u32(sg.make_thresholds(sg.make_schedule(0, 0.1, 3.0, 256)))
+    for L in (32, 64):
+        inst = sg.Instance.generate(L, wl.instance_seed("sa_batch", 64000 + L), chain=1)
+        for n in (1, 16):
+            res = {}
+            for name in ("wide", "group"):
+                def fn():
+                    if name == "wide":
+                        return sg.sa_anneal(inst, thr, n, 5)
+                    return sg.sa_anneal_variant(inst, thr, n, 5, sg.selected_variant(L))
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(a.steps):
+                    r = fn()
+                torch.cuda.synchronize()
+                res[name] = ((time.perf_counter() - t0) * 1e3 / a.steps, r[1])
+            out["rows"].append({"L": L, "replicas": n, "wide_ms": res["wide"][0], "group_ms": res["group"][0],
+                                "identical": bool(torch.equal(res["wide"][1], res["group"][1]))})
+    return out
+
+
+def pticm(a, sg, wl, torch):
+    """PT with isoenergetic cluster moves at the tuned ladder (L = 12, T = 4
+    slots x 2 copies, beta 0.2 -> 2.0, moves on every slot), 128 runs x 200
+    steps: spin-flip attempts/s and time per step."""
+    inst = sg.Instance.generate(12, wl.instance_seed("pt", 12), chain=0)
+    T, runs, steps = 4, 128, 200
+    beta = sg.make_schedule(1, 0.2, 2.0, T)
+    thr = sg.to_device_u32(sg.make_thresholds(beta))
+    M = sg.exchange_table_width(beta)
+    thrx = sg.to_device_u32(sg.make_exchange_thresholds(beta, M))
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def fn():
+        res["out"] = sg.pticm_run(inst, thr, thrx, runs, steps, wl.philox_seed("pt"), icm_from=0, want_icm=True)
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    att = runs * steps * 2 * T * 12 ** 3
+    fl = res["out"]["icm_flipped"].float().mean().item()
+    return {"metric": "spin-flip attempts/s (PT+ICM L=12, 2 x 4 walkers, 128 runs x 200 steps)",
+            "value": att / (ms * 1e-3), "unit": "spin-flip attempts/s", "ms_per_call": ms,
+            "us_per_step": ms * 1e3 / steps, "sites_flipped_per_step_mean": fl}
+
+
 def tuning(a, sg, wl, torch):
     """App. D form: SA beta-range grid, PT ladder grid, then alpha(eps) at
     eps = 3, 4, 5 % for SA and PT with the chosen parameters."""
@@ -240,5 +290,6 @@ def tuning(a, sg, wl, torch):
 
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tuning": tuning}[name]
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tuning": tuning,
+          "wide": wide, "pticm": pticm}[name]
     return fn(a, sg, wl, torch)

@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_init(SaJob job)
         if (neg) w |= 0xFFu << (8 * b);
     }
     job.workspace[t] = w;
+    if (rem == 0) job.energy[r] = 0;   // accumulated by k_wide_final
 }
 
 // One colour phase of sweep si (row si of the thresholds): lane = dword m of
@@ -86,20 +87,27 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_phase(SaJob job, int si, 
     rep[at] = own ^ WideCol<L>::template accept_dword<false>(kbm, u, reinterpret_cast<const char *>(tb), m, dE);
 }
 
-// Per replica (one work group each): natural-order spins back to the
-// caller and the energy of Eq. 1 as the sum over colour-0 sites of s_i h_i.
+// Natural-order spins back to the caller and the energy of Eq. 1 (the sum
+// over colour-0 sites of s_i h_i), kWideFinalGroups work groups per replica,
+// each on a slice of the quads and colour-0 dwords; the energy (zeroed by
+// k_wide_init) accumulates atomically.
+constexpr int kWideFinalGroups = 64;
+
 template <int L>
 __global__ __launch_bounds__(kWideThreads) void k_wide_final(SaJob job)
 {
     using G = Geo<L>;
-    const int r = static_cast<int>(blockIdx.x);
+    const int r = static_cast<int>(blockIdx.x) / kWideFinalGroups;
+    const int part = static_cast<int>(blockIdx.x) - r * kWideFinalGroups;
     const int tid = static_cast<int>(threadIdx.x);
     const uint32_t *rep = job.workspace + static_cast<int64_t>(r) * G::SPIN_DW;
     const uint8_t *repb = reinterpret_cast<const uint8_t *>(rep);
-    for (int q = tid; q < G::N / 4; q += kWideThreads)
+    constexpr int QN = G::N / 4, QP = (QN + kWideFinalGroups - 1) / kWideFinalGroups;
+    for (int q = part * QP + tid; q < min(QN, (part + 1) * QP); q += kWideThreads)
         store_spins_one<L, kDwordMajor>(repb, q, job.spins + static_cast<int64_t>(r) * G::N);
+    constexpr int WN = G::C * G::NC, WP = (WN + kWideFinalGroups - 1) / kWideFinalGroups;
     int32_t e = 0;
-    for (int w = tid; w < G::C * G::NC; w += kWideThreads) {
+    for (int w = part * WP + tid; w < min(WN, (part + 1) * WP); w += kWideThreads) {
         const int m = w / G::NC;
         const int col = w - m * G::NC;
         const uint32_t own = rep[spin_at<L, kDwordMajor>(0, col, m)];
@@ -109,13 +117,13 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_final(SaJob job)
              static_cast<int32_t>(byte_sum(kbm & WideCol<L>::valid(m)));
     }
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-    __shared__ int32_t part[kWideThreads / 64];
-    if ((tid & 63) == 0) part[tid >> 6] = e;
+    __shared__ int32_t partial[kWideThreads / 64];
+    if ((tid & 63) == 0) partial[tid >> 6] = e;
     __syncthreads();
     if (tid == 0) {
         int32_t total = 0;
-        for (int i = 0; i < kWideThreads / 64; ++i) total += part[i];
-        job.energy[r] = total;
+        for (int i = 0; i < kWideThreads / 64; ++i) total += partial[i];
+        if (total != 0) atomicAdd(&job.energy[r], total);
     }
 }
 
@@ -133,7 +141,8 @@ static int launch_wide(const SaJob &job, hipStream_t st)
     const dim3 grid(static_cast<uint32_t>((n_phase + kWideThreads - 1) / kWideThreads));
     for (int si = 0; si < job.n_sweeps; ++si)
         for (int c = 0; c < 2; ++c) hipLaunchKernelGGL(k_wide_phase<L>, grid, dim3(kWideThreads), 0, st, job, si, c);
-    hipLaunchKernelGGL(k_wide_final<L>, dim3(static_cast<uint32_t>(job.n_rep)), dim3(kWideThreads), 0, st, job);
+    hipLaunchKernelGGL(k_wide_final<L>, dim3(static_cast<uint32_t>(job.n_rep) * kWideFinalGroups),
+                       dim3(kWideThreads), 0, st, job);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "sa_anneal (wide): launch failed: %s", hipGetErrorString(err));
     return SG_OK;
