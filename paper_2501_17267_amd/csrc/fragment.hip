@@ -8,8 +8,9 @@
 //
 // One launch per phase, one work group per (core, run).  The group's R
 // waves anneal R independent copies of the fragment in LDS (wave r = copy
-// r); each keeps its copy's spins, the fragment's in-fragment couplings and
-// the free/fixed mask on chip for the whole anneal.  The copy with the
+// r), each on its own without block barriers: the spins of its copy, the
+// fragment's in-fragment couplings and per-colour lists of the free sites
+// with their neighbours stay on chip for the whole anneal.  The copy with the
 // lowest in-fragment energy (lowest r among equals) gives the core's spins.
 // A fragment site counts as fixed exactly when its core belongs to an
 // earlier phase, so a group never reads the cores written in its own phase.
@@ -80,13 +81,31 @@ __device__ inline void frag_phase_core(const FragJob &j, int q, int idx, int &bx
     bz = q - bx - by;
 }
 
+// Orders one wave's LDS accesses across this point (a memory fence at
+// wavefront scope for the compiler, then the wave barrier)
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// A free site of one colour, as the sweep reads it: its local index and its
+// six neighbours' (the site itself where the neighbour is outside the
+// fragment: its coupling is zero there)
+struct FragSite {
+    uint16_t j, nb[6];
+    uint16_t pad;
+};
+
 __global__ __launch_bounds__(kFragMaxR * 64) void k_frag_phase(FragJob job, int q, int count)
 {
     __shared__ int8_t s_spin[kFragMaxR][kFragMaxSites];
     __shared__ int8_t s_J[6][kFragMaxSites];
     __shared__ uint8_t s_free[kFragMaxSites];
-    __shared__ uint32_t s_thr[SG_K_MAX];
+    __shared__ FragSite s_site[kFragMaxSites];          // free sites, colour 0 then colour 1
+    __shared__ uint32_t s_thr[kFragMaxR][SG_K_MAX];    // each wave's copy of the current row
     __shared__ int32_t s_E[kFragMaxR];
+    __shared__ int32_t s_nsite[2];
     __shared__ int32_t s_best;
 
     const int tid = static_cast<int>(threadIdx.x);
@@ -120,6 +139,39 @@ __global__ __launch_bounds__(kFragMaxR * 64) void k_frag_phase(FragJob job, int 
         for (int d = 0; d < 6; ++d) s_J[d][j] = in[d] ? job.J[d * N + g] : 0;
     }
     __syncthreads();
+    // lists of the free sites of each colour (wave 0, 64 sites per ballot)
+    if (tid < 64) {
+        int base = 0;
+        for (int col = 0; col < 2; ++col) {
+            for (int j0 = 0; j0 < n3; j0 += 64) {
+                const int j = j0 + tid;
+                bool take = false;
+                int lx = 0, ly = 0, lz = 0;
+                if (j < n3) {
+                    lx = j % l;
+                    ly = (j / l) % l;
+                    lz = j / (l * l);
+                    take = s_free[j] && ((opar + lx + ly + lz) & 1) == col;
+                }
+                const uint64_t mask = __ballot(take);
+                if (take) {
+                    const int pos = base + __popcll(mask & ((1ull << tid) - 1ull));
+                    FragSite fs;
+                    fs.j = static_cast<uint16_t>(j);
+                    fs.nb[0] = static_cast<uint16_t>(lx + 1 < l ? j + 1 : j);
+                    fs.nb[1] = static_cast<uint16_t>(lx > 0 ? j - 1 : j);
+                    fs.nb[2] = static_cast<uint16_t>(ly + 1 < l ? j + l : j);
+                    fs.nb[3] = static_cast<uint16_t>(ly > 0 ? j - l : j);
+                    fs.nb[4] = static_cast<uint16_t>(lz + 1 < l ? j + l * l : j);
+                    fs.nb[5] = static_cast<uint16_t>(lz > 0 ? j - l * l : j);
+                    fs.pad = 0;
+                    s_site[pos] = fs;
+                }
+                base += __popcll(mask);
+            }
+            if (tid == 0) s_nsite[col] = base;   // end of colour col's list
+        }
+    }
     for (int p = tid; p < job.R * n3; p += NT) {
         const int r = p / n3, j = p - r * n3;
         if (s_free[j]) {
@@ -127,36 +179,37 @@ __global__ __launch_bounds__(kFragMaxR * 64) void k_frag_phase(FragJob job, int 
             s_spin[r][j] = (u.w[0] >> 31) ? -1 : 1;
         }
     }
+    __syncthreads();
 
-    // ---- sweeps: wave r anneals copy r -----------------------------------------
+    // ---- sweeps: wave r anneals copy r on its own ------------------------------
+    // Nothing below is shared between waves until the energies, so the waves
+    // need no block barrier: a wave's LDS accesses execute in issue order,
+    // and wave_sync keeps the compiler from moving them across a phase.
     const int r = tid >> 6, lane = tid & 63;
     int8_t *sp = s_spin[r];
+    uint32_t *thr_r = s_thr[r];
+    const int n0 = s_nsite[0], n01 = s_nsite[1];
     for (int s = 0; s < job.S; ++s) {
-        __syncthreads();
-        if (tid < job.K) s_thr[tid] = job.thr[static_cast<int64_t>(s) * job.K + tid];
-        __syncthreads();
+        if (lane < job.K) thr_r[lane] = job.thr[static_cast<int64_t>(s) * job.K + lane];
+        wave_sync();
         for (int col = 0; col < 2; ++col) {
-            for (int j = lane; j < n3; j += 64) {
-                const int lx = j % l, ly = (j / l) % l, lz = j / (l * l);
-                if (!s_free[j] || ((opar + lx + ly + lz) & 1) != col) continue;
-                // neighbours outside the fragment carry a zero coupling; their
-                // index is clamped to the site itself
-                const int nbr[6] = {lx + 1 < l ? j + 1 : j, lx > 0 ? j - 1 : j,
-                                    ly + 1 < l ? j + l : j, ly > 0 ? j - l : j,
-                                    lz + 1 < l ? j + l * l : j, lz > 0 ? j - l * l : j};
+            const int e0 = col ? n0 : 0, e1 = col ? n01 : n0;
+            for (int e = e0 + lane; e < e1; e += 64) {
+                const FragSite fs = s_site[e];
+                const int j = fs.j;
                 int hf = 0;
 #pragma unroll
-                for (int d = 0; d < 6; ++d) hf += s_J[d][j] * sp[nbr[d]];
+                for (int d = 0; d < 6; ++d) hf += s_J[d][j] * sp[fs.nb[d]];
                 const int kk = -sp[j] * hf;
                 bool acc = kk <= 0;
                 if (!acc && kk <= job.K) {
                     const Rand4 u = philox10(static_cast<uint32_t>(r * n3 + j), 2u * static_cast<uint32_t>(s) +
                                              static_cast<uint32_t>(col), k, run, job.k0, job.k1);
-                    acc = u.w[0] < s_thr[kk - 1];
+                    acc = u.w[0] < thr_r[kk - 1];
                 }
                 if (acc) sp[j] = static_cast<int8_t>(-sp[j]);
             }
-            __syncthreads();
+            wave_sync();
         }
     }
 
