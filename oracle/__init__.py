@@ -5,6 +5,7 @@ Test infrastructure: only ``tests/``, ``__graft_entry__.smoke()`` and the
 library never loads it and shares no code with it.
 
 Every wrapper returns NumPy arrays; all arithmetic happens in the C file.
+The tensor-network fragment oracle is plain NumPy, in ``oracle/tn.py``.
 """
 from __future__ import annotations
 
