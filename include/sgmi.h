@@ -252,6 +252,91 @@ typedef struct sg_frag_args {
 int sg_fragment_decimate(const sg_instance *inst, const sg_frag_args *args, const uint32_t *thr,
                          int8_t *spins_out, int32_t *energy_out, void *stream);
 
+/* ---- tensor-network fragment decimation (Sec. I, App. A-C) ----------------
+ * The paper's own subsystem optimiser: single-spin decimation from the
+ * exact marginal of a fragment.  The fragment of site i is the l^3 cube,
+ * l = 2h + 1, centred on i (periodic wrap, l < L); only bonds with both
+ * ends in the cube belong to it.  Sites are decimated phase by phase,
+ *   order 0: phase (x mod P) + P((y mod P) + P(z mod P)), P = 1 + h,
+ *            L % P == 0 (no two sites of a phase share a fragment);
+ *   order 1: phase x + y + z (diagonal wavefront).
+ * A fragment site decimated in an earlier phase is fixed at its value, the
+ * others are free (every site of a phase sees the state at the phase's
+ * start).  With Z(s) = sum over the free spins other than i of
+ * exp(-beta E_frag), E_frag the fragment's share of Eq. 1 with s_i = s,
+ * site i takes +1 when ln Z(+1) >= ln Z(-1), else -1 (its most probable
+ * value).  The tropical form (the zero-temperature variant named in
+ * Sec. III) uses the least fragment energy E(s) instead: +1 when
+ * E(+1) <= E(-1).  The contraction is exact (no truncation): each
+ * fragment's free spins are summed out one by one over a table indexed by
+ * the spins still connected to the summed part.
+ *
+ * A plan holds what depends only on (L, h, order): the distinct fragment
+ * shapes and the elimination program of each.  Tables of at most
+ * 2^lds_max_bits entries are contracted in LDS by one work group; larger
+ * ones live in the caller's workspace (at most 2^SG_TN_MAX_BITS entries).
+ */
+#define SG_TN_MAX_HALO 2     /* l = 2h + 1 <= 5, the paper's fragment edge */
+#define SG_TN_MAX_BITS 26    /* largest elimination table: 2^26 doubles */
+#define SG_TN_LDS_BITS 13    /* default LDS tier: tables of up to 2^13 entries */
+typedef struct sg_tn_plan sg_tn_plan;
+
+typedef struct sg_tn_plan_info {
+    int32_t L, halo, order, lds_max_bits;
+    int32_t n_phases;
+    int32_t n_shapes;            /* distinct free-site patterns */
+    int32_t max_bits;            /* largest table, log2 entries */
+    int32_t n_lds_sites;         /* sites contracted in LDS */
+    int32_t n_hbm_sites;         /* sites contracted in the workspace */
+    int32_t max_steps;           /* most eliminations of one fragment */
+    double pair_updates;         /* table pair updates per decimation (both values of s_i) */
+} sg_tn_plan_info;
+
+/* Plan the decimation of an L^3 lattice with fragment halo h (1..SG_TN_MAX_HALO)
+ * in phase order `order`.  lds_max_bits: the largest table contracted in LDS
+ * (0 = SG_TN_LDS_BITS; 1..SG_TN_LDS_BITS).  Host work only: the plan's
+ * tables go to the device on its first decimation and stay there until
+ * sg_tn_plan_destroy; a plan serves the device current at that call.
+ * SG_EINVAL for shapes outside the rules above, SG_EUNSUPPORTED when a
+ * fragment would need a table above 2^SG_TN_MAX_BITS. */
+int sg_tn_plan_create(int32_t L, int32_t halo, int32_t order, int32_t lds_max_bits, sg_tn_plan **out);
+int sg_tn_plan_info_get(const sg_tn_plan *plan, sg_tn_plan_info *out);
+int sg_tn_plan_destroy(sg_tn_plan *plan);
+
+/* The plan's elimination programs, for inspection (host memory; any
+ * pointer may be NULL to skip that array; the counts are always written):
+ *   shapes [n_shapes][4]: table bits W, step count, first step, and a 6-bit
+ *     mask of the centre's neighbour directions that are fixed sites;
+ *   steps [n_steps][8]: eliminated local site j = lx + l (ly + l lz), its
+ *     table slot, then per direction +x,-x,+y,-y,+z,-z the neighbour's code:
+ *     its slot (>= 0), -1 fixed, -2 the centre, -3 outside or eliminated;
+ *   items [N][2]: every site as (centre site, shape), phase by phase. */
+int sg_tn_plan_program(const sg_tn_plan *plan, int32_t *n_shapes, int32_t *shapes, int32_t *n_steps,
+                       int16_t *steps, int32_t *n_items, int32_t *items);
+
+/* Workspace for n_inst instances: `full` = 0 gives the least that works
+ * (the workspace tables are then processed in several passes), 1 the size
+ * that holds the largest phase of all instances at once. */
+int64_t sg_tn_workspace_bytes(const sg_tn_plan *plan, int32_t n_inst, int32_t full);
+
+typedef struct sg_tn_args {
+    const int8_t *J;     /* device int8 [n_inst][6][N], values in [-4, 4] */
+    int32_t n_inst;      /* instances of the plan's L decimated together */
+    int32_t tropical;    /* 1: min-plus form (beta unused) */
+    double beta;         /* inverse temperature, 0 < beta <= 20 */
+    int8_t *spins_out;   /* device int8 [n_inst][N]: the decimated spins */
+    double *score_out;   /* device double [n_inst][N] or NULL: each site's
+                            ln Z(+1) - ln Z(-1), or E(-1) - E(+1) when tropical */
+    int32_t *energy_out; /* device int32 [n_inst] or NULL: Eq. 1 of spins_out */
+    void *workspace;     /* device, workspace_bytes >= sg_tn_workspace_bytes(plan, n_inst, 0) */
+    int64_t workspace_bytes;
+} sg_tn_args;
+
+/* Decimate n_inst instances with the plan.  SG_EINVAL for bad arguments
+ * (including a workspace below the minimum), SG_ENOMEM when the plan's
+ * first upload fails. */
+int sg_tn_decimate(sg_tn_plan *plan, const sg_tn_args *args, void *stream);
+
 /* Energy (Eq. 1) of n_rep configurations spins [n_rep][N] -> energy [n_rep]. */
 int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t *energy_out,
            void *stream);

@@ -65,6 +65,20 @@ class sg_frag_args(ctypes.Structure):
                 ("n_sweeps", ctypes.c_int32), ("K", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
+class sg_tn_plan_info(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("halo", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("lds_max_bits", ctypes.c_int32), ("n_phases", ctypes.c_int32), ("n_shapes", ctypes.c_int32),
+                ("max_bits", ctypes.c_int32), ("n_lds_sites", ctypes.c_int32), ("n_hbm_sites", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("pair_updates", ctypes.c_double)]
+
+
+class sg_tn_args(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_void_p), ("n_inst", ctypes.c_int32), ("tropical", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("spins_out", ctypes.c_void_p), ("score_out", ctypes.c_void_p),
+                ("energy_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
 class sg_sa_variant(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("replicas_per_group", ctypes.c_int32),
                 ("waves_per_group", ctypes.c_int32), ("both_encodings", ctypes.c_int32),
@@ -133,6 +147,13 @@ def lib() -> ctypes.CDLL:
     L.sg_pticm_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pticm_args), vp, vp, vp, vp, vp, vp, vp,
                                vp, vp]
     L.sg_fragment_decimate.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_frag_args), vp, vp, vp, vp]
+    L.sg_tn_plan_create.argtypes = [c.c_int32, c.c_int32, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
+    L.sg_tn_plan_info_get.argtypes = [vp, c.POINTER(sg_tn_plan_info)]
+    L.sg_tn_plan_destroy.argtypes = [vp]
+    L.sg_tn_plan_program.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.sg_tn_workspace_bytes.argtypes = [vp, c.c_int32, c.c_int32]
+    L.sg_tn_workspace_bytes.restype = c.c_int64
+    L.sg_tn_decimate.argtypes = [vp, c.POINTER(sg_tn_args), vp]
     L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
     L.sg_batch_create.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
     L.sg_batch_launch.argtypes = [vp, vp]
@@ -149,7 +170,8 @@ def lib() -> ctypes.CDLL:
                "sg_sa_anneal_variant", "sg_autotune_sa", "sg_batch_create", "sg_batch_launch", "sg_batch_info", "sg_batch_kernels",
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
-               "sg_fragment_decimate", "sg_pticm_run",
+               "sg_fragment_decimate", "sg_pticm_run", "sg_tn_plan_create", "sg_tn_plan_info_get",
+               "sg_tn_plan_destroy", "sg_tn_plan_program", "sg_tn_decimate",
                "pt_run", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
@@ -501,6 +523,78 @@ def fragment_decimate(inst: Instance, thr, core: int, halo: int, replicas: int, 
                                       _dptr(sp, "spins"), _dptr(en, "energy"), _stream(stream)),
            "sg_fragment_decimate")
     return sp, en
+
+
+class TnPlan:
+    """Plan of the tensor-network fragment decimation of an L^3 lattice with
+    fragment edge 2 halo + 1 in phase order `order` (host work only)."""
+
+    def __init__(self, L: int, halo: int, order: int = 1, lds_max_bits: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().sg_tn_plan_create(L, halo, order, lds_max_bits, ctypes.byref(h)), "sg_tn_plan_create")
+        self._h = h
+        self.L, self.halo, self.order = int(L), int(halo), int(order)
+
+    def info(self) -> dict:
+        out = sg_tn_plan_info()
+        _check(lib().sg_tn_plan_info_get(self._h, ctypes.byref(out)), "sg_tn_plan_info_get")
+        return {name: getattr(out, name) for name, _ in sg_tn_plan_info._fields_}
+
+    def program(self):
+        """(shapes [S][4] int32, steps [T][8] int16, items [N][2] int32)."""
+        ns, nt, ni = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sg_tn_plan_program(self._h, ctypes.byref(ns), None, ctypes.byref(nt), None,
+                                        ctypes.byref(ni), None), "sg_tn_plan_program")
+        shapes = np.zeros((ns.value, 4), np.int32)
+        steps = np.zeros((max(nt.value, 1), 8), np.int16)
+        items = np.zeros((ni.value, 2), np.int32)
+        _check(lib().sg_tn_plan_program(self._h, ctypes.byref(ns), _np_ptr(shapes), ctypes.byref(nt),
+                                        _np_ptr(steps), ctypes.byref(ni), _np_ptr(items)), "sg_tn_plan_program")
+        return shapes, steps[:nt.value], items
+
+    def workspace_bytes(self, n_inst: int, full: bool = True) -> int:
+        n = int(lib().sg_tn_workspace_bytes(self._h, n_inst, 1 if full else 0))
+        if n < 0:
+            _check(n, "sg_tn_workspace_bytes")
+        return n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sg_tn_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tn_decimate(plan: TnPlan, J, beta: float = 2.0, tropical: bool = False, want_score: bool = True,
+                workspace=None, stream=None):
+    """Decimate a batch of instances of the plan's L.  J: device int8
+    [n_inst][6][N] (or [6][N], or an Instance).  Returns (spins int8
+    [n_inst][N], energy int32 [n_inst], score float64 [n_inst][N] or None)."""
+    import torch
+    if isinstance(J, Instance):
+        J = J.J
+    if J.dim() == 2:
+        J = J.unsqueeze(0)
+    J = J.contiguous()
+    n_inst, N = int(J.shape[0]), int(J.shape[2])
+    dev = J.device
+    sp = torch.empty((n_inst, N), dtype=torch.int8, device=dev)
+    en = torch.empty(n_inst, dtype=torch.int32, device=dev)
+    sc = torch.empty((n_inst, N), dtype=torch.float64, device=dev) if want_score else None
+    if workspace is None:
+        nbytes = plan.workspace_bytes(n_inst, full=True)
+        workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+    args = sg_tn_args(J=J.data_ptr(), n_inst=n_inst, tropical=1 if tropical else 0, beta=float(beta),
+                      spins_out=sp.data_ptr(), score_out=sc.data_ptr() if sc is not None else None,
+                      energy_out=en.data_ptr(), workspace=workspace.data_ptr(),
+                      workspace_bytes=workspace.numel() * workspace.element_size())
+    _check(lib().sg_tn_decimate(plan._h, ctypes.byref(args), _stream(stream)), "sg_tn_decimate")
+    return sp, en, sc
 
 
 def energy(inst: Instance, spins, stream=None):

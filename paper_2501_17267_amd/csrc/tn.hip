@@ -1,0 +1,617 @@
+// tn.hip -- tensor-network fragment decimation (Sec. I, App. A-C) on the
+// device: exact contraction of every fragment's free spins, one table per
+// (site, value of the site), phase by phase.
+//
+// LDS tier: one work group holds a table of up to 2^lds_bits doubles (or
+// int32 for the tropical form) and runs the whole elimination program of
+// its shape, one block barrier per eliminated spin.
+// Workspace tier: larger tables live in the caller's workspace; every
+// elimination step is one launch over all tables of a batch, kTnPairsPerThread
+// pair updates per thread.
+// A sum-product table is renormalised after every step by the power of two
+// that brings its largest entry into [1, 2) (exact scaling, the exponents
+// summed beside it), so no table overflows or underflows for beta <= 20.
+// A decision kernel per phase turns the two results of each site into its
+// spin and score.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "common.hpp"
+#include "tn.hpp"
+#include "variants.hpp"
+
+namespace sg {
+
+namespace {
+
+constexpr int kTnHMax = 24;                  // |h_v| <= 6 * 4
+constexpr int kTnWeights = 2 * kTnHMax + 1;  // exp(-beta k), k = -24..24
+constexpr double kLn2 = 0.69314718055994530942;
+
+struct TnWeights {
+    double w[kTnWeights];
+};
+
+struct TnJob {
+    const int8_t *J;       // [n_inst][6][N]
+    int8_t *dec;           // [n_inst][N]
+    double *score;         // [n_inst][N] or null
+    const TnShape *shapes;
+    const TnStep *steps;
+    const TnItem *items;
+    double *res;           // [n_inst][items of the phase][2]
+    int32_t L, h, l;
+    int64_t N;
+    double beta;
+};
+
+// the eliminated spin's slot, its active neighbours' slots and couplings, and
+// the field from fixed and centre neighbours
+struct TnDesc {
+    uint32_t slots;        // 5 bits per direction
+    int8_t J[6];           // 0 where the neighbour is not active
+    int16_t hc;
+    int32_t a;
+};
+
+__device__ inline int64_t tn_wrap_site(const TnJob &jb, int64_t site, int dx, int dy, int dz)
+{
+    const int L = jb.L;
+    const int x = static_cast<int>(site % L), y = static_cast<int>((site / L) % L),
+              z = static_cast<int>(site / (static_cast<int64_t>(L) * L));
+    const int gx = (x + dx + L) % L, gy = (y + dy + L) % L, gz = (z + dz + L) % L;
+    return gx + static_cast<int64_t>(L) * (gy + static_cast<int64_t>(L) * gz);
+}
+
+// global index of local fragment site j of the fragment centred on `site`
+__device__ inline int64_t tn_local_site(const TnJob &jb, int64_t site, int j)
+{
+    const int l = jb.l;
+    return tn_wrap_site(jb, site, j % l - jb.h, (j / l) % l - jb.h, j / (l * l) - jb.h);
+}
+
+__device__ inline int64_t tn_nbr(const TnJob &jb, int64_t g, int d)
+{
+    return tn_wrap_site(jb, g, (d == 0) - (d == 1), (d == 2) - (d == 3), (d == 4) - (d == 5));
+}
+
+__device__ inline TnDesc tn_desc(const TnJob &jb, const int8_t *J, const int8_t *dec, int64_t site, int sc,
+                                 const TnStep &st)
+{
+    TnDesc D{};
+    const int64_t g = tn_local_site(jb, site, st.lv);
+    int hc = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int code = st.code[d];
+        if (code == kTnNone) continue;
+        const int Jd = J[d * jb.N + g];
+        if (code >= 0) {
+            D.J[d] = static_cast<int8_t>(Jd);
+            D.slots |= static_cast<uint32_t>(code) << (5 * d);
+        } else if (code == kTnConst) {
+            hc += Jd * dec[tn_nbr(jb, g, d)];
+        } else {
+            hc += Jd * sc;
+        }
+    }
+    D.hc = static_cast<int16_t>(hc);
+    D.a = st.a;
+    return D;
+}
+
+// energy of the centre's bonds to fixed fragment sites, at centre value sc
+__device__ inline int tn_centre_energy(const TnJob &jb, const int8_t *J, const int8_t *dec, int64_t site, int sc,
+                                       const TnShape &sh)
+{
+    int e = 0;
+    for (int d = 0; d < 6; ++d)
+        if (sh.ccode[d] == kTnConst) e += J[d * jb.N + site] * dec[tn_nbr(jb, site, d)];
+    return e * sc;
+}
+
+__device__ inline int tn_field(const TnDesc &D, uint32_t I0)
+{
+    int hh = D.hc;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) hh += D.J[d] * (1 - 2 * static_cast<int>((I0 >> ((D.slots >> (5 * d)) & 31u)) & 1u));
+    // |h| <= 24 for couplings in [-4, 4]; the clamp only keeps the weight
+    // lookup inside its table for invalid couplings
+    return min(max(hh, -kTnHMax), kTnHMax);
+}
+
+__device__ inline uint32_t tn_pair_index(uint32_t p, int a)
+{
+    const uint32_t low = (1u << a) - 1u;
+    return ((p >> a) << (a + 1)) | (p & low);
+}
+
+// (T0 w(+1) + T1 w(-1)) scale with both products rounded before the sum (no
+// fused multiply-add): a table and
+// its mirror image (every spin flipped) then give bit-identical results, so
+// a site whose fragment has no fixed coupling scores exactly 0
+__device__ inline double tn_pair_sum(double t0, double w0, double t1, double w1, double scale)
+{
+#pragma clang fp contract(off)
+    const double p0 = t0 * w0;
+    const double p1 = t1 * w1;
+    return (p0 + p1) * scale;
+}
+
+// ln Z of a finished table: ln T + (applied exponents) ln 2 - beta E_centre
+__device__ inline double tn_log_result(double t, int64_t e_sum, double beta, int es)
+{
+#pragma clang fp contract(off)
+    const double a = log(t);
+    const double b = static_cast<double>(e_sum) * kLn2;
+    const double c = beta * static_cast<double>(es);
+    return (a + b) - c;
+}
+
+__device__ inline int wave_max_int(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---- LDS tier ---------------------------------------------------------------
+
+template <bool TROP>
+__global__ __launch_bounds__(kTnThreads) void k_tn_lds(TnJob jb, TnWeights wt, int item0, int n_items_q, int n_lds,
+                                                        int tab_bytes, int desc_steps)
+{
+    using T = typename std::conditional<TROP, int32_t, double>::type;
+    extern __shared__ __align__(16) char smem[];
+    T *tab = reinterpret_cast<T *>(smem);
+    TnDesc *desc = reinterpret_cast<TnDesc *>(smem + tab_bytes);
+    double *w = reinterpret_cast<double *>(desc + desc_steps);
+    int *s_emax = reinterpret_cast<int *>(w + kTnWeights);   // [2][waves]
+
+    const int tid = static_cast<int>(threadIdx.x);
+    const int gid = static_cast<int>(blockIdx.x);
+    const int cv = gid & 1;
+    const int k = (gid >> 1) % n_lds;
+    const int inst = (gid >> 1) / n_lds;
+    const int sc = cv ? -1 : 1;
+    const TnItem it = jb.items[item0 + k];
+    const TnShape sh = jb.shapes[it.shape];
+    const int8_t *J = jb.J + static_cast<int64_t>(inst) * 6 * jb.N;
+    const int8_t *dec = jb.dec + static_cast<int64_t>(inst) * jb.N;
+    const int W = sh.W, ns = sh.n_steps;
+
+    for (int t = tid; t < ns; t += kTnThreads) desc[t] = tn_desc(jb, J, dec, it.site, sc, jb.steps[sh.step0 + t]);
+    if (!TROP)
+        for (int i = tid; i < kTnWeights; i += kTnThreads) w[i] = wt.w[i];
+    for (int i = tid; i < (1 << W); i += kTnThreads) tab[i] = TROP ? T(0) : T(1);
+    __syncthreads();
+
+    const int half = W > 0 ? 1 << (W - 1) : 0;
+    double scale = 1.0;
+    int e_prev = 0, e_sum = 0;
+    for (int t = 0; t < ns; ++t) {
+        if (!TROP && t > 0) {
+            e_sum += e_prev;
+            scale = ldexp(1.0, -e_prev);
+        }
+        const TnDesc D = desc[t];
+        const uint32_t abit = 1u << D.a;
+        double m = 0.0;
+        for (int p = tid; p < half; p += kTnThreads) {
+            const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
+            const int hh = tn_field(D, I0);
+            T v;
+            if (TROP) {
+                v = min(tab[I0] + hh, tab[I1] - hh);
+            } else {
+                v = tn_pair_sum(tab[I0], w[kTnHMax + hh], tab[I1], w[kTnHMax - hh], scale);
+                m = fmax(m, static_cast<double>(v));
+            }
+            tab[I0] = v;
+            tab[I1] = v;
+        }
+        if (!TROP) {
+            const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
+            if ((tid & 63) == 0) s_emax[(t & 1) * (kTnThreads / 64) + (tid >> 6)] = e;
+        }
+        __syncthreads();
+        if (!TROP) {
+            int e = INT_MIN;
+            for (int i = 0; i < kTnThreads / 64; ++i) e = max(e, s_emax[(t & 1) * (kTnThreads / 64) + i]);
+            e_prev = e;
+        }
+    }
+    if (tid == 0) {
+        const int es = tn_centre_energy(jb, J, dec, it.site, sc, sh);
+        double r;
+        if (TROP)
+            r = static_cast<double>(static_cast<int64_t>(tab[0]) + es);
+        else
+            r = tn_log_result(static_cast<double>(tab[0]), e_sum, jb.beta, es);
+        jb.res[(static_cast<int64_t>(inst) * n_items_q + k) * 2 + cv] = r;
+    }
+}
+
+// ---- workspace tier ----------------------------------------------------------
+
+// a batch: instances [b0, b0 + nb), workspace items [k0, k1) of one phase
+// (indices relative to the phase's first workspace item)
+struct TnBatch {
+    int32_t item_hbm0;          // index in items of the phase's first workspace item
+    int32_t res_k0;             // position of that item among the phase's items
+    int32_t n_items_q;
+    int32_t k0, k1, b0, nb;
+    int32_t steps;              // row length of emax
+    const int64_t *entry_pre;   // the phase's segment of the prefix arrays
+    const int64_t *block_pre;
+    int64_t ents_per_inst, blks_per_inst;
+    int32_t *emax;              // [tables][steps]
+    int32_t *es;                // [tables]
+    void *tables;
+};
+
+__device__ inline void tn_batch_table(const TnBatch &bt, int64_t blk, int &bi, int &k, int &cv, int64_t &tblk)
+{
+    bi = static_cast<int>(blk / bt.blks_per_inst);
+    const int64_t rb = blk - static_cast<int64_t>(bi) * bt.blks_per_inst + bt.block_pre[bt.k0];
+    int lo = bt.k0, hi = bt.k1 - 1;   // last k with block_pre[k] <= rb
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bt.block_pre[mid] <= rb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    k = lo;
+    const int64_t within = rb - bt.block_pre[k];
+    const int64_t per = (bt.block_pre[k + 1] - bt.block_pre[k]) / 2;
+    cv = static_cast<int>(within / per);
+    tblk = within - cv * per;
+}
+
+template <bool TROP>
+__global__ void k_tn_hbm_prep(TnJob jb, TnBatch bt)
+{
+    const int64_t tix = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int nk = bt.k1 - bt.k0;
+    if (tix >= static_cast<int64_t>(bt.nb) * nk * 2) return;
+    const int cv = static_cast<int>(tix & 1);
+    const int k = bt.k0 + static_cast<int>((tix >> 1) % nk);
+    const int inst = bt.b0 + static_cast<int>((tix >> 1) / nk);
+    const TnItem it = jb.items[bt.item_hbm0 + k];
+    const TnShape sh = jb.shapes[it.shape];
+    bt.es[tix] = tn_centre_energy(jb, jb.J + static_cast<int64_t>(inst) * 6 * jb.N,
+                                  jb.dec + static_cast<int64_t>(inst) * jb.N, it.site, cv ? -1 : 1, sh);
+    for (int t = 0; t < bt.steps; ++t) bt.emax[tix * bt.steps + t] = INT_MIN;
+}
+
+template <bool TROP>
+__global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnJob jb, TnBatch bt, TnWeights wt, int t)
+{
+    using T = typename std::conditional<TROP, int32_t, double>::type;
+    __shared__ double w[kTnWeights];
+    __shared__ int s_emax[kTnThreads / 64];
+    const int tid = static_cast<int>(threadIdx.x);
+    int bi, k, cv;
+    int64_t tblk;
+    tn_batch_table(bt, blockIdx.x, bi, k, cv, tblk);
+    const TnItem it = jb.items[bt.item_hbm0 + k];
+    const TnShape sh = jb.shapes[it.shape];
+    if (t >= sh.n_steps) return;   // uniform over the work group
+    const int inst = bt.b0 + bi;
+    const int64_t tix = (static_cast<int64_t>(bi) * (bt.k1 - bt.k0) + (k - bt.k0)) * 2 + cv;
+    T *tab = reinterpret_cast<T *>(bt.tables) + static_cast<int64_t>(bi) * bt.ents_per_inst +
+             (bt.entry_pre[k] - bt.entry_pre[bt.k0]) + (static_cast<int64_t>(cv) << sh.W);
+    const TnDesc D = tn_desc(jb, jb.J + static_cast<int64_t>(inst) * 6 * jb.N,
+                             jb.dec + static_cast<int64_t>(inst) * jb.N, it.site, cv ? -1 : 1,
+                             jb.steps[sh.step0 + t]);
+    if (!TROP) {
+        for (int i = tid; i < kTnWeights; i += kTnThreads) w[i] = wt.w[i];
+        __syncthreads();
+    }
+    const double scale = (!TROP && t > 0) ? ldexp(1.0, -bt.emax[tix * bt.steps + t - 1]) : 1.0;
+    const int64_t half = int64_t{1} << (sh.W - 1);
+    const uint32_t abit = 1u << D.a;
+    double m = 0.0;
+    for (int r = 0; r < kTnPairsPerThread; ++r) {
+        const int64_t p = (tblk * kTnPairsPerThread + r) * kTnThreads + tid;
+        if (p >= half) break;
+        const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
+        const int hh = tn_field(D, I0);
+        T v;
+        if (TROP) {
+            const T t0 = t > 0 ? tab[I0] : T(0), t1 = t > 0 ? tab[I1] : T(0);
+            v = min(t0 + hh, t1 - hh);
+        } else {
+            const T t0 = t > 0 ? tab[I0] : T(1), t1 = t > 0 ? tab[I1] : T(1);
+            v = tn_pair_sum(t0, w[kTnHMax + hh], t1, w[kTnHMax - hh], scale);
+            m = fmax(m, static_cast<double>(v));
+        }
+        tab[I0] = v;
+        tab[I1] = v;
+    }
+    if (!TROP) {
+        const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
+        if ((tid & 63) == 0) s_emax[tid >> 6] = e;
+        __syncthreads();
+        if (tid == 0) {
+            int em = INT_MIN;
+            for (int i = 0; i < kTnThreads / 64; ++i) em = max(em, s_emax[i]);
+            atomicMax(&bt.emax[tix * bt.steps + t], em);
+        }
+    }
+}
+
+template <bool TROP>
+__global__ void k_tn_hbm_final(TnJob jb, TnBatch bt)
+{
+    using T = typename std::conditional<TROP, int32_t, double>::type;
+    const int64_t tix = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int nk = bt.k1 - bt.k0;
+    if (tix >= static_cast<int64_t>(bt.nb) * nk * 2) return;
+    const int cv = static_cast<int>(tix & 1);
+    const int kk = static_cast<int>((tix >> 1) % nk);
+    const int bi = static_cast<int>((tix >> 1) / nk);
+    const int k = bt.k0 + kk;
+    const TnShape sh = jb.shapes[jb.items[bt.item_hbm0 + k].shape];
+    const T *tab = reinterpret_cast<const T *>(bt.tables) + static_cast<int64_t>(bi) * bt.ents_per_inst +
+                   (bt.entry_pre[k] - bt.entry_pre[bt.k0]) + (static_cast<int64_t>(cv) << sh.W);
+    double r;
+    if (TROP) {
+        r = static_cast<double>(static_cast<int64_t>(tab[0]) + bt.es[tix]);
+    } else {
+        int64_t e_sum = 0;
+        for (int t = 0; t + 1 < sh.n_steps; ++t) e_sum += bt.emax[tix * bt.steps + t];
+        r = tn_log_result(static_cast<double>(tab[0]), e_sum, jb.beta, bt.es[tix]);
+    }
+    const int inst = bt.b0 + bi;
+    jb.res[(static_cast<int64_t>(inst) * bt.n_items_q + bt.res_k0 + k) * 2 + cv] = r;
+}
+
+// ---- decisions ----------------------------------------------------------------
+
+template <bool TROP>
+__global__ void k_tn_decide(TnJob jb, int item0, int n_items_q, int n_inst)
+{
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(n_inst) * n_items_q) return;
+    const int inst = static_cast<int>(t / n_items_q);
+    const int k = static_cast<int>(t - static_cast<int64_t>(inst) * n_items_q);
+    const double zp = jb.res[t * 2], zm = jb.res[t * 2 + 1];
+    const double r = TROP ? zm - zp : zp - zm;
+    const int64_t g = static_cast<int64_t>(inst) * jb.N + jb.items[item0 + k].site;
+    jb.dec[g] = r >= 0.0 ? 1 : -1;
+    if (jb.score) jb.score[g] = r;
+}
+
+__global__ void k_tn_zero(int8_t *p, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ---- host side -----------------------------------------------------------------
+
+inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t{255}; }
+
+int64_t res_bytes(const sg_tn_plan &p, int n_inst)
+{
+    return align256(static_cast<int64_t>(p.max_items) * n_inst * 2 * sizeof(double));
+}
+
+int64_t batch_bytes(int64_t tables, int64_t entries, int steps)
+{
+    return align256(tables * steps * 4) + align256(tables * 4) + align256(entries * 8);
+}
+
+int lds_bytes(const TnPhase &P, bool trop, int &tab_bytes)
+{
+    const int ent = 1 << P.lds_bits;
+    tab_bytes = static_cast<int>(align256(static_cast<int64_t>(ent) * (trop ? 4 : 8)));
+    return tab_bytes + P.lds_steps * static_cast<int>(sizeof(TnDesc)) + kTnWeights * 8 + 2 * (kTnThreads / 64) * 4;
+}
+
+int upload(sg_tn_plan &p)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SG_EDEVICE, "sg_tn_decimate: hipGetDevice");
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (p.device >= 0) {
+        if (p.device != dev)
+            return fail(SG_EINVAL, "sg_tn_decimate: the plan was uploaded to device %d, current is %d", p.device, dev);
+        return SG_OK;
+    }
+    auto put = [](void **d, const void *h, size_t n) {
+        if (n == 0) n = 8;
+        if (hipMalloc(d, n) != hipSuccess) return false;
+        return h == nullptr || hipMemcpy(*d, h, n, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    const bool ok = put(&p.d_shapes, p.shapes.data(), p.shapes.size() * sizeof(TnShape)) &&
+                    put(&p.d_steps, p.steps.empty() ? nullptr : p.steps.data(), p.steps.size() * sizeof(TnStep)) &&
+                    put(&p.d_items, p.items.data(), p.items.size() * sizeof(TnItem)) &&
+                    put(&p.d_entry_pre, p.hbm_entry_pre.data(), p.hbm_entry_pre.size() * sizeof(int64_t)) &&
+                    put(&p.d_block_pre, p.hbm_block_pre.data(), p.hbm_block_pre.size() * sizeof(int64_t));
+    if (!ok) {
+        for (void **d : {&p.d_shapes, &p.d_steps, &p.d_items, &p.d_entry_pre, &p.d_block_pre})
+            if (*d) (void)hipFree(*d), *d = nullptr;
+        return fail(SG_ENOMEM, "sg_tn_decimate: uploading the plan");
+    }
+    // the largest LDS work group of the plan
+    int need = 0;
+    for (const TnPhase &P : p.phases) {
+        int tb;
+        if (P.n_lds) need = std::max(need, lds_bytes(P, false, tb));
+    }
+    if (need > 0) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_tn_lds<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_tn_lds<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess)
+            return fail(SG_EDEVICE, "sg_tn_decimate: LDS attribute (%d bytes)", need);
+    }
+    p.device = dev;
+    return SG_OK;
+}
+
+template <bool TROP>
+int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
+{
+    TnJob jb{};
+    jb.J = a.J;
+    jb.dec = a.spins_out;
+    jb.score = a.score_out;
+    jb.shapes = static_cast<const TnShape *>(p.d_shapes);
+    jb.steps = static_cast<const TnStep *>(p.d_steps);
+    jb.items = static_cast<const TnItem *>(p.d_items);
+    jb.res = static_cast<double *>(a.workspace);
+    jb.L = p.L;
+    jb.h = p.h;
+    jb.l = p.l;
+    jb.N = static_cast<int64_t>(p.L) * p.L * p.L;
+    jb.beta = a.beta;
+    TnWeights wt{};
+    for (int k = -kTnHMax; k <= kTnHMax; ++k) wt.w[k + kTnHMax] = TROP ? 0.0 : std::exp(-a.beta * k);
+    const int n_inst = a.n_inst;
+    char *heavy = static_cast<char *>(a.workspace) + res_bytes(p, n_inst);
+    const int64_t cap = a.workspace_bytes - res_bytes(p, n_inst);
+
+    (void)hipGetLastError();
+    const int64_t nz = static_cast<int64_t>(n_inst) * jb.N;
+    hipLaunchKernelGGL(k_tn_zero, dim3(static_cast<uint32_t>((nz + 255) / 256)), dim3(256), 0, st, a.spins_out, nz);
+    for (const TnPhase &P : p.phases) {
+        const int n_items_q = P.n_lds + P.n_hbm;
+        if (n_items_q == 0) continue;
+        if (P.n_lds) {
+            int tb;
+            const int bytes = lds_bytes(P, TROP, tb);
+            hipLaunchKernelGGL(k_tn_lds<TROP>, dim3(static_cast<uint32_t>(n_inst) * P.n_lds * 2), dim3(kTnThreads),
+                               bytes, st, jb, wt, P.item0, n_items_q, P.n_lds, tb, P.lds_steps);
+        }
+        if (P.n_hbm) {
+            const int64_t *epre = p.hbm_entry_pre.data() + P.hbm0;
+            const int64_t *bpre = p.hbm_block_pre.data() + P.hbm0;
+            const int steps = P.hbm_steps;
+            const int64_t inst_bytes = batch_bytes(2 * P.n_hbm, epre[P.n_hbm], steps);
+            // batches: whole instances when one fits, else item ranges of one instance
+            struct Range { int b0, nb, k0, k1; };
+            std::vector<Range> batches;
+            if (inst_bytes <= cap) {
+                int per = static_cast<int>(std::min<int64_t>(n_inst, 1));
+                while (per < n_inst && batch_bytes(2 * P.n_hbm * int64_t{per + 1}, epre[P.n_hbm] * (per + 1), steps) <= cap)
+                    ++per;
+                for (int b = 0; b < n_inst; b += per) batches.push_back({b, std::min(per, n_inst - b), 0, P.n_hbm});
+            } else {
+                for (int b = 0; b < n_inst; ++b)
+                    for (int k0 = 0; k0 < P.n_hbm;) {
+                        int k1 = k0 + 1;
+                        while (k1 < P.n_hbm && batch_bytes(2 * int64_t{k1 + 1 - k0}, epre[k1 + 1] - epre[k0], steps) <= cap)
+                            ++k1;
+                        batches.push_back({b, 1, k0, k1});
+                        k0 = k1;
+                    }
+            }
+            for (const Range &R : batches) {
+                TnBatch bt{};
+                bt.item_hbm0 = P.item0 + P.n_lds;
+                bt.res_k0 = P.n_lds;
+                bt.n_items_q = n_items_q;
+                bt.k0 = R.k0;
+                bt.k1 = R.k1;
+                bt.b0 = R.b0;
+                bt.nb = R.nb;
+                bt.steps = steps;
+                bt.entry_pre = static_cast<const int64_t *>(p.d_entry_pre) + P.hbm0;
+                bt.block_pre = static_cast<const int64_t *>(p.d_block_pre) + P.hbm0;
+                bt.ents_per_inst = epre[R.k1] - epre[R.k0];
+                bt.blks_per_inst = bpre[R.k1] - bpre[R.k0];
+                const int64_t nt = static_cast<int64_t>(R.nb) * (R.k1 - R.k0) * 2;
+                bt.emax = reinterpret_cast<int32_t *>(heavy);
+                bt.es = reinterpret_cast<int32_t *>(heavy + align256(nt * steps * 4));
+                bt.tables = heavy + align256(nt * steps * 4) + align256(nt * 4);
+                int max_steps = 0;
+                for (int k = R.k0; k < R.k1; ++k)
+                    max_steps = std::max(max_steps, p.shapes[p.items[bt.item_hbm0 + k].shape].n_steps);
+                hipLaunchKernelGGL(k_tn_hbm_prep<TROP>, dim3(static_cast<uint32_t>((nt + 63) / 64)), dim3(64), 0, st,
+                                   jb, bt);
+                const dim3 grid(static_cast<uint32_t>(R.nb * bt.blks_per_inst));
+                for (int t = 0; t < max_steps; ++t)
+                    hipLaunchKernelGGL(k_tn_hbm_step<TROP>, grid, dim3(kTnThreads), 0, st, jb, bt, wt, t);
+                hipLaunchKernelGGL(k_tn_hbm_final<TROP>, dim3(static_cast<uint32_t>((nt + 63) / 64)), dim3(64), 0,
+                                   st, jb, bt);
+            }
+        }
+        const int64_t nd = static_cast<int64_t>(n_inst) * n_items_q;
+        hipLaunchKernelGGL(k_tn_decide<TROP>, dim3(static_cast<uint32_t>((nd + 255) / 256)), dim3(256), 0, st, jb,
+                           P.item0, n_items_q, n_inst);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return fail(SG_EDEVICE, "sg_tn_decimate: launch failed: %s", hipGetErrorString(err));
+    }
+    if (a.energy_out)
+        for (int b = 0; b < n_inst; ++b) {
+            const int rc = launch_energy(a.J + static_cast<int64_t>(b) * 6 * jb.N, p.L, 1,
+                                         a.spins_out + static_cast<int64_t>(b) * jb.N, a.energy_out + b, st);
+            if (rc != SG_OK) return rc;
+        }
+    return SG_OK;
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int64_t sg_tn_workspace_bytes(const sg_tn_plan *p, int32_t n_inst, int32_t full)
+{
+    if (!p || n_inst < 1) return fail(SG_EINVAL, "sg_tn_workspace_bytes: plan NULL or n_inst = %d", n_inst);
+    clear_error();
+    int64_t heavy = 0;
+    for (const TnPhase &P : p->phases) {
+        if (!P.n_hbm) continue;
+        const int64_t *epre = p->hbm_entry_pre.data() + P.hbm0;
+        if (full) {
+            heavy = std::max(heavy, batch_bytes(int64_t{2} * P.n_hbm * n_inst, epre[P.n_hbm] * n_inst, P.hbm_steps));
+        } else {
+            for (int k = 0; k < P.n_hbm; ++k)
+                heavy = std::max(heavy, batch_bytes(2, epre[k + 1] - epre[k], P.hbm_steps));
+        }
+    }
+    return res_bytes(*p, n_inst) + heavy;
+}
+
+int sg_tn_plan_destroy(sg_tn_plan *p)
+{
+    if (!p) return fail(SG_EINVAL, "sg_tn_plan_destroy: NULL plan");
+    clear_error();
+    for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre, p->d_block_pre})
+        if (d) (void)hipFree(d);
+    delete p;
+    return SG_OK;
+}
+
+int sg_tn_decimate(sg_tn_plan *p, const sg_tn_args *a, void *stream)
+{
+    if (!p || !a) return fail(SG_EINVAL, "sg_tn_decimate: NULL plan or args");
+    if (!a->J || !a->spins_out || !a->workspace) return fail(SG_EINVAL, "sg_tn_decimate: NULL J, spins_out or workspace");
+    if (a->n_inst < 1 || a->n_inst > (1 << 16)) return fail(SG_EINVAL, "sg_tn_decimate: n_inst = %d", a->n_inst);
+    if (!a->tropical && !(a->beta > 0.0 && a->beta <= 20.0))
+        return fail(SG_EINVAL, "sg_tn_decimate: beta = %g outside (0, 20]", a->beta);
+    const int64_t need = sg_tn_workspace_bytes(p, a->n_inst, 0);
+    if (a->workspace_bytes < need)
+        return fail(SG_EINVAL, "sg_tn_decimate: workspace %lld bytes < %lld", static_cast<long long>(a->workspace_bytes),
+                    static_cast<long long>(need));
+    if (reinterpret_cast<uintptr_t>(a->workspace) % 256 != 0)
+        return fail(SG_EINVAL, "sg_tn_decimate: workspace must be 256-byte aligned");
+    clear_error();
+    int rc = upload(*p);
+    if (rc != SG_OK) return rc;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    return a->tropical ? run<true>(*p, *a, st) : run<false>(*p, *a, st);
+}
+
+}  // extern "C"
