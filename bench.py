@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "tuning", "wide", "pticm", "microbench",
+    ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "tn", "tuning", "wide", "pticm", "microbench",
                              "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
@@ -191,6 +191,40 @@ def cpu_baseline_fragment(sg, wl, L=12):
             "sample": f"{cores} instances at L={L}, one per thread, {dt:.1f} s"}
 
 
+def cpu_baseline_tn(sg, wl, L=20, n_sites=48):
+    """The oracle's exact fragment marginals (l = 5, beta = 2) for a sample
+    of sites of the first L = 20 instance: random sites whose tables fit the
+    LDS tier (the oracle's elimination order makes the larger ones take
+    minutes each), with the decimated state of the GPU's own run as the
+    fixed spins, one site per task on the host threads."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    from oracle import tn
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    spec = wl.tn_instances(L, 1)[0]
+    J, _, _ = sg.make_instance(L, spec.cls, spec.seed)
+    J = np.asarray(J).reshape(6, L ** 3)
+    plan = sg.TnPlan(L, 2, 1)
+    dec = sg.tn_decimate(plan, torch.from_numpy(J).cuda(), 2.0, want_score=False)[0].cpu().numpy()[0]
+    shapes, _, items = plan.program()
+    light = [int(site) for site, s in items if shapes[s][0] <= plan.info()["lds_max_bits"]]
+    rng = np.random.default_rng(7)
+    sites = [int(i) for i in rng.choice(light, n_sites, replace=False)]
+    ph = tn.phases(1, L, 2)
+
+    def one(i):
+        return tn.site_score(L, J, tn.fixed_before(dec, ph, i), i, 2, 2.0)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, sites))
+    dt = time.perf_counter() - t0
+    return {"value": n_sites / dt, "unit": f"site marginals/s at L={L}, l=5 (LDS-tier sites)", "cores": cores,
+            "kind": "oracle", "sample": f"{n_sites} random LDS-tier sites of one L={L} instance in {dt:.1f} s"}
+
+
 # ---------------------------------------------------------------------------
 
 def main():
@@ -221,6 +255,9 @@ def main():
         if a.workload == "fragment" and not a.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline_fragment(sg, wl)
+        if a.workload == "tn" and not a.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_tn(sg, wl)
         print(json.dumps(out))
         return
 

@@ -307,12 +307,18 @@ int sg_tn_plan_destroy(sg_tn_plan *plan);
  * pointer may be NULL to skip that array; the counts are always written):
  *   shapes [n_shapes][4]: table bits W, step count, first step, and a 6-bit
  *     mask of the centre's neighbour directions that are fixed sites;
- *   steps [n_steps][8]: eliminated local site j = lx + l (ly + l lz), its
- *     table slot, then per direction +x,-x,+y,-y,+z,-z the neighbour's code:
- *     its slot (>= 0), -1 fixed, -2 the centre, -3 outside or eliminated;
+ *   steps [n_steps][16]: eliminated local site j = lx + l (ly + l lz), its
+ *     table slot a, then per direction +x,-x,+y,-y,+z,-z the neighbour's
+ *     code: its slot (>= 0), -1 fixed, -2 the centre, -3 outside or
+ *     eliminated; then the workspace tier's canonical-entry bookkeeping:
+ *     whether slot a was active before the step, the number of runs of
+ *     consecutive canonical slots other than a, their total length, the
+ *     mask of slots that become active at the step (a excluded), and the
+ *     runs packed four to an int: byte r%4 of int 12 + r/4 = start of run
+ *     r, of int 14 + r/4 = its length;
  *   items [N][2]: every site as (centre site, shape), phase by phase. */
 int sg_tn_plan_program(const sg_tn_plan *plan, int32_t *n_shapes, int32_t *shapes, int32_t *n_steps,
-                       int16_t *steps, int32_t *n_items, int32_t *items);
+                       int32_t *steps, int32_t *n_items, int32_t *items);
 
 /* Workspace for n_inst instances: `full` = 0 gives the least that works
  * (the workspace tables are then processed in several passes), 1 the size

@@ -541,12 +541,12 @@ class TnPlan:
         return {name: getattr(out, name) for name, _ in sg_tn_plan_info._fields_}
 
     def program(self):
-        """(shapes [S][4] int32, steps [T][8] int16, items [N][2] int32)."""
+        """(shapes [S][4] int32, steps [T][16] int32, items [N][2] int32)."""
         ns, nt, ni = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().sg_tn_plan_program(self._h, ctypes.byref(ns), None, ctypes.byref(nt), None,
                                         ctypes.byref(ni), None), "sg_tn_plan_program")
         shapes = np.zeros((ns.value, 4), np.int32)
-        steps = np.zeros((max(nt.value, 1), 8), np.int16)
+        steps = np.zeros((max(nt.value, 1), 16), np.int32)
         items = np.zeros((ni.value, 2), np.int32)
         _check(lib().sg_tn_plan_program(self._h, ctypes.byref(ns), _np_ptr(shapes), ctypes.byref(nt),
                                         _np_ptr(steps), ctypes.byref(ni), _np_ptr(items)), "sg_tn_plan_program")

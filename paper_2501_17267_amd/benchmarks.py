@@ -228,6 +228,16 @@ def fragment(a, sg, wl, torch):
     return res
 
 
+def tn(a, sg, wl, torch):
+    """The tensor-network subsystem optimiser (exact l = 5 fragment
+    marginals at beta = 2): eps_lin and time vs L, beta and l studies."""
+    from . import tn_study
+    import sys
+    res = tn_study.run(torch, log=lambda *m: print("[tn]", *m, file=sys.stderr, flush=True))
+    res["metric"] = "eps_lin and time per instance of the tensor-network meta-heuristic vs L"
+    return res
+
+
 def wide(a, sg, wl, torch):
     """One anneal of few replicas of L = 32 and 64 (256 sweeps): the
     multi-work-group path that sa_anneal picks by itself, against the
@@ -290,6 +300,6 @@ def tuning(a, sg, wl, torch):
 
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tuning": tuning,
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tn": tn, "tuning": tuning,
           "wide": wide, "pticm": pticm}[name]
     return fn(a, sg, wl, torch)

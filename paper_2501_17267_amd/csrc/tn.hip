@@ -6,8 +6,9 @@
 // int32 for the tropical form) and runs the whole elimination program of
 // its shape, one block barrier per eliminated spin.
 // Workspace tier: larger tables live in the caller's workspace; every
-// elimination step is one launch over all tables of a batch, kTnPairsPerThread
-// pair updates per thread.
+// elimination step is one launch over all tables of a batch that updates only
+// the canonical entries of its table (see TnStep), up to kTnPairsPerThread
+// reads per thread.
 // A sum-product table is renormalised after every step by the power of two
 // that brings its largest entry into [1, 2) (exact scaling, the exponents
 // summed beside it), so no table overflows or underflows for beta <= 20.
@@ -239,100 +240,184 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_lds(TnJob jb, TnWeights wt, i
 // ---- workspace tier ----------------------------------------------------------
 
 // a batch: instances [b0, b0 + nb), workspace items [k0, k1) of one phase
-// (indices relative to the phase's first workspace item)
+// (indices relative to the phase's first workspace item); its tables are
+// numbered tix = ((instance - b0) (k1 - k0) + (item - k0)) 2 + (centre value)
 struct TnBatch {
     int32_t item_hbm0;          // index in items of the phase's first workspace item
     int32_t res_k0;             // position of that item among the phase's items
     int32_t n_items_q;
     int32_t k0, k1, b0, nb;
-    int32_t steps;              // row length of emax
-    const int64_t *entry_pre;   // the phase's segment of the prefix arrays
-    const int64_t *block_pre;
-    int64_t ents_per_inst, blks_per_inst;
+    int32_t steps;              // row length of desc and emax
+    const int64_t *entry_pre;   // the phase's segment of the table-entry prefix
+    int64_t ents_per_inst;
+    struct TnTab *tabs;         // [tables]
+    struct TnDescX *desc;       // [tables][steps]
+    int32_t *blkpre;            // [steps][k1 - k0 + 1]: work groups of the items before
+                                //   (one table; every instance and value has the same)
     int32_t *emax;              // [tables][steps]
     int32_t *es;                // [tables]
     void *tables;
 };
 
-__device__ inline void tn_batch_table(const TnBatch &bt, int64_t blk, int &bi, int &k, int &cv, int64_t &tblk)
-{
-    bi = static_cast<int>(blk / bt.blks_per_inst);
-    const int64_t rb = blk - static_cast<int64_t>(bi) * bt.blks_per_inst + bt.block_pre[bt.k0];
-    int lo = bt.k0, hi = bt.k1 - 1;   // last k with block_pre[k] <= rb
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bt.block_pre[mid] <= rb)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    k = lo;
-    const int64_t within = rb - bt.block_pre[k];
-    const int64_t per = (bt.block_pre[k + 1] - bt.block_pre[k]) / 2;
-    cv = static_cast<int>(within / per);
-    tblk = within - cv * per;
-}
+struct TnTab {
+    int32_t n_steps, W;
+    int64_t off;                // first entry of the table in the batch's table region
+};
 
-template <bool TROP>
+// one elimination step of one workspace table, ready to use: the field
+// terms of the eliminated spin and the canonical bookkeeping of TnStep
+struct __align__(16) TnDescX {
+    TnDesc d;
+    uint32_t newmask;
+    uint8_t a_active, n_runs, n_base, pad;
+    uint8_t run_start[8];
+    uint8_t run_len[8];
+    uint32_t pad2[2];
+};
+static_assert(sizeof(TnDescX) == 48, "TnDescX layout");
+
+// per (table, step): the step's descriptor; per table: its header, the
+// centre's fixed-bond energy, and the exponent slots cleared
 __global__ void k_tn_hbm_prep(TnJob jb, TnBatch bt)
 {
-    const int64_t tix = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int nk = bt.k1 - bt.k0;
-    if (tix >= static_cast<int64_t>(bt.nb) * nk * 2) return;
+    const int64_t nt = static_cast<int64_t>(bt.nb) * nk * 2;
+    if (gid >= nt * bt.steps) return;
+    const int64_t tix = gid / bt.steps;
+    const int t = static_cast<int>(gid - tix * bt.steps);
     const int cv = static_cast<int>(tix & 1);
     const int k = bt.k0 + static_cast<int>((tix >> 1) % nk);
-    const int inst = bt.b0 + static_cast<int>((tix >> 1) / nk);
+    const int bi = static_cast<int>((tix >> 1) / nk);
+    const int inst = bt.b0 + bi;
     const TnItem it = jb.items[bt.item_hbm0 + k];
     const TnShape sh = jb.shapes[it.shape];
-    bt.es[tix] = tn_centre_energy(jb, jb.J + static_cast<int64_t>(inst) * 6 * jb.N,
-                                  jb.dec + static_cast<int64_t>(inst) * jb.N, it.site, cv ? -1 : 1, sh);
-    for (int t = 0; t < bt.steps; ++t) bt.emax[tix * bt.steps + t] = INT_MIN;
+    const int8_t *J = jb.J + static_cast<int64_t>(inst) * 6 * jb.N;
+    const int8_t *dec = jb.dec + static_cast<int64_t>(inst) * jb.N;
+    bt.emax[gid] = INT_MIN;
+    if (t == 0) {
+        TnTab tb;
+        tb.n_steps = sh.n_steps;
+        tb.W = sh.W;
+        tb.off = static_cast<int64_t>(bi) * bt.ents_per_inst + (bt.entry_pre[k] - bt.entry_pre[bt.k0]) +
+                 (static_cast<int64_t>(cv) << sh.W);
+        bt.tabs[tix] = tb;
+        bt.es[tix] = tn_centre_energy(jb, J, dec, it.site, cv ? -1 : 1, sh);
+    }
+    if (t < sh.n_steps) {
+        const TnStep st = jb.steps[sh.step0 + t];
+        TnDescX x{};
+        x.d = tn_desc(jb, J, dec, it.site, cv ? -1 : 1, st);
+        x.newmask = st.newmask;
+        x.a_active = st.a_active;
+        x.n_runs = st.n_runs;
+        x.n_base = st.n_base;
+        for (int r = 0; r < 8; ++r) {
+            x.run_start[r] = st.run_start[r];
+            x.run_len[r] = st.run_len[r];
+        }
+        bt.desc[gid] = x;
+    }
 }
 
+// per step: the prefix over the batch's items of their work groups
+// (tn_table_blocks of the step's canonical reads; none once an item is done)
+__global__ void k_tn_hbm_blocks(TnJob jb, TnBatch bt)
+{
+    const int t = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= bt.steps) return;
+    const int nk = bt.k1 - bt.k0;
+    constexpr int per = kTnThreads * kTnPairsPerThread;
+    int32_t acc = 0;
+    for (int kk = 0; kk < nk; ++kk) {
+        bt.blkpre[t * (nk + 1) + kk] = acc;
+        const TnShape sh = jb.shapes[jb.items[bt.item_hbm0 + bt.k0 + kk].shape];
+        if (t < sh.n_steps) acc += ((1 << jb.steps[sh.step0 + t].n_base) + per - 1) / per;
+    }
+    bt.blkpre[t * (nk + 1) + nk] = acc;
+}
+
+// canonical index of read item p: the bits of p deposited into the step's runs
+__device__ inline uint32_t tn_deposit(uint32_t p, const TnDescX &x)
+{
+    uint32_t I = 0;
+    int used = 0;
+    for (int r = 0; r < x.n_runs; ++r) {
+        const int len = x.run_len[r];
+        I |= ((p >> used) & ((1u << len) - 1u)) << x.run_start[r];
+        used += len;
+    }
+    return I;
+}
+
+// step t of every table of the batch that has one: blocks_t work groups per
+// (instance, centre value), each item's share given by the prefix blkpre[t]
 template <bool TROP>
-__global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnJob jb, TnBatch bt, TnWeights wt, int t)
+__global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeights wt, int t, int blocks_t)
 {
     using T = typename std::conditional<TROP, int32_t, double>::type;
     __shared__ double w[kTnWeights];
     __shared__ int s_emax[kTnThreads / 64];
     const int tid = static_cast<int>(threadIdx.x);
-    int bi, k, cv;
-    int64_t tblk;
-    tn_batch_table(bt, blockIdx.x, bi, k, cv, tblk);
-    const TnItem it = jb.items[bt.item_hbm0 + k];
-    const TnShape sh = jb.shapes[it.shape];
-    if (t >= sh.n_steps) return;   // uniform over the work group
-    const int inst = bt.b0 + bi;
-    const int64_t tix = (static_cast<int64_t>(bi) * (bt.k1 - bt.k0) + (k - bt.k0)) * 2 + cv;
-    T *tab = reinterpret_cast<T *>(bt.tables) + static_cast<int64_t>(bi) * bt.ents_per_inst +
-             (bt.entry_pre[k] - bt.entry_pre[bt.k0]) + (static_cast<int64_t>(cv) << sh.W);
-    const TnDesc D = tn_desc(jb, jb.J + static_cast<int64_t>(inst) * 6 * jb.N,
-                             jb.dec + static_cast<int64_t>(inst) * jb.N, it.site, cv ? -1 : 1,
-                             jb.steps[sh.step0 + t]);
+    const int nk = bt.k1 - bt.k0;
+    const int64_t g = static_cast<int64_t>(blockIdx.x) / blocks_t;   // (instance, value)
+    const int rb = static_cast<int>(static_cast<int64_t>(blockIdx.x) - g * blocks_t);
+    const int32_t *pre = bt.blkpre + static_cast<int64_t>(t) * (nk + 1);
+    int lo = 0, hi = nk - 1;   // the item: last kk with pre[kk] <= rb
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= rb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int bpt = pre[lo + 1] - pre[lo];
+    const int64_t tblk = rb - pre[lo];
+    const int64_t tix = ((g >> 1) * nk + lo) * 2 + (g & 1);
+    const TnTab tb = bt.tabs[tix];
+    const TnDescX x = bt.desc[tix * bt.steps + t];
+    T *tab = reinterpret_cast<T *>(bt.tables) + tb.off;
     if (!TROP) {
         for (int i = tid; i < kTnWeights; i += kTnThreads) w[i] = wt.w[i];
         __syncthreads();
     }
     const double scale = (!TROP && t > 0) ? ldexp(1.0, -bt.emax[tix * bt.steps + t - 1]) : 1.0;
-    const int64_t half = int64_t{1} << (sh.W - 1);
-    const uint32_t abit = 1u << D.a;
-    double m = 0.0;
+    const int64_t items = int64_t{1} << x.n_base;
+    const int64_t stride = static_cast<int64_t>(bpt) * kTnThreads;
+    const uint32_t abit = 1u << x.d.a;
+    const uint32_t nm = x.newmask;
+    // all reads first (several in flight per thread), then the updates
+    uint32_t I[kTnPairsPerThread];
+    T t0[kTnPairsPerThread], t1[kTnPairsPerThread];
+#pragma unroll
     for (int r = 0; r < kTnPairsPerThread; ++r) {
-        const int64_t p = (tblk * kTnPairsPerThread + r) * kTnThreads + tid;
-        if (p >= half) break;
-        const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
-        const int hh = tn_field(D, I0);
-        T v;
-        if (TROP) {
-            const T t0 = t > 0 ? tab[I0] : T(0), t1 = t > 0 ? tab[I1] : T(0);
-            v = min(t0 + hh, t1 - hh);
-        } else {
-            const T t0 = t > 0 ? tab[I0] : T(1), t1 = t > 0 ? tab[I1] : T(1);
-            v = tn_pair_sum(t0, w[kTnHMax + hh], t1, w[kTnHMax - hh], scale);
-            m = fmax(m, static_cast<double>(v));
+        const int64_t p = tblk * kTnThreads + tid + r * stride;
+        I[r] = tn_deposit(static_cast<uint32_t>(p), x);
+        t0[r] = t1[r] = TROP ? T(0) : T(1);
+        if (p < items && t > 0) {
+            t0[r] = tab[I[r]];
+            t1[r] = x.a_active ? tab[I[r] | abit] : t0[r];
         }
-        tab[I0] = v;
-        tab[I1] = v;
+    }
+    double m = 0.0;
+#pragma unroll
+    for (int r = 0; r < kTnPairsPerThread; ++r) {
+        const int64_t p = tblk * kTnThreads + tid + r * stride;
+        if (p >= items) break;
+        uint32_t c = 0;
+        do {
+            const uint32_t O = I[r] | c;
+            const int hh = tn_field(x.d, O);
+            T v;
+            if (TROP) {
+                v = min(t0[r] + hh, t1[r] - hh);
+            } else {
+                v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
+                m = fmax(m, static_cast<double>(v));
+            }
+            tab[O] = v;
+            c = (c - nm) & nm;
+        } while (c != 0);
     }
     if (!TROP) {
         const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
@@ -354,22 +439,19 @@ __global__ void k_tn_hbm_final(TnJob jb, TnBatch bt)
     const int nk = bt.k1 - bt.k0;
     if (tix >= static_cast<int64_t>(bt.nb) * nk * 2) return;
     const int cv = static_cast<int>(tix & 1);
-    const int kk = static_cast<int>((tix >> 1) % nk);
+    const int k = bt.k0 + static_cast<int>((tix >> 1) % nk);
     const int bi = static_cast<int>((tix >> 1) / nk);
-    const int k = bt.k0 + kk;
-    const TnShape sh = jb.shapes[jb.items[bt.item_hbm0 + k].shape];
-    const T *tab = reinterpret_cast<const T *>(bt.tables) + static_cast<int64_t>(bi) * bt.ents_per_inst +
-                   (bt.entry_pre[k] - bt.entry_pre[bt.k0]) + (static_cast<int64_t>(cv) << sh.W);
+    const TnTab tb = bt.tabs[tix];
+    const T *tab = reinterpret_cast<const T *>(bt.tables) + tb.off;
     double r;
     if (TROP) {
         r = static_cast<double>(static_cast<int64_t>(tab[0]) + bt.es[tix]);
     } else {
         int64_t e_sum = 0;
-        for (int t = 0; t + 1 < sh.n_steps; ++t) e_sum += bt.emax[tix * bt.steps + t];
+        for (int t = 0; t + 1 < tb.n_steps; ++t) e_sum += bt.emax[tix * bt.steps + t];
         r = tn_log_result(static_cast<double>(tab[0]), e_sum, jb.beta, bt.es[tix]);
     }
-    const int inst = bt.b0 + bi;
-    jb.res[(static_cast<int64_t>(inst) * bt.n_items_q + bt.res_k0 + k) * 2 + cv] = r;
+    jb.res[(static_cast<int64_t>(bt.b0 + bi) * bt.n_items_q + bt.res_k0 + k) * 2 + cv] = r;
 }
 
 // ---- decisions ----------------------------------------------------------------
@@ -403,9 +485,13 @@ int64_t res_bytes(const sg_tn_plan &p, int n_inst)
     return align256(static_cast<int64_t>(p.max_items) * n_inst * 2 * sizeof(double));
 }
 
-int64_t batch_bytes(int64_t tables, int64_t entries, int steps)
+// workspace of a batch of nk items: headers, descriptors, work-group
+// prefixes, exponents, energies, tables
+int64_t batch_bytes(int64_t tables, int64_t entries, int steps, int64_t nk)
 {
-    return align256(tables * steps * 4) + align256(tables * 4) + align256(entries * 8);
+    return align256(tables * static_cast<int64_t>(sizeof(TnTab))) +
+           align256(tables * steps * static_cast<int64_t>(sizeof(TnDescX))) + align256(steps * (nk + 1) * 4) +
+           align256(tables * steps * 4) + align256(tables * 4) + align256(entries * 8);
 }
 
 int lds_bytes(const TnPhase &P, bool trop, int &tab_bytes)
@@ -433,10 +519,9 @@ int upload(sg_tn_plan &p)
     const bool ok = put(&p.d_shapes, p.shapes.data(), p.shapes.size() * sizeof(TnShape)) &&
                     put(&p.d_steps, p.steps.empty() ? nullptr : p.steps.data(), p.steps.size() * sizeof(TnStep)) &&
                     put(&p.d_items, p.items.data(), p.items.size() * sizeof(TnItem)) &&
-                    put(&p.d_entry_pre, p.hbm_entry_pre.data(), p.hbm_entry_pre.size() * sizeof(int64_t)) &&
-                    put(&p.d_block_pre, p.hbm_block_pre.data(), p.hbm_block_pre.size() * sizeof(int64_t));
+                    put(&p.d_entry_pre, p.hbm_entry_pre.data(), p.hbm_entry_pre.size() * sizeof(int64_t));
     if (!ok) {
-        for (void **d : {&p.d_shapes, &p.d_steps, &p.d_items, &p.d_entry_pre, &p.d_block_pre})
+        for (void **d : {&p.d_shapes, &p.d_steps, &p.d_items, &p.d_entry_pre})
             if (*d) (void)hipFree(*d), *d = nullptr;
         return fail(SG_ENOMEM, "sg_tn_decimate: uploading the plan");
     }
@@ -493,22 +578,23 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
         }
         if (P.n_hbm) {
             const int64_t *epre = p.hbm_entry_pre.data() + P.hbm0;
-            const int64_t *bpre = p.hbm_block_pre.data() + P.hbm0;
             const int steps = P.hbm_steps;
-            const int64_t inst_bytes = batch_bytes(2 * P.n_hbm, epre[P.n_hbm], steps);
+            const int64_t inst_bytes = batch_bytes(2 * P.n_hbm, epre[P.n_hbm], steps, P.n_hbm);
             // batches: whole instances when one fits, else item ranges of one instance
             struct Range { int b0, nb, k0, k1; };
             std::vector<Range> batches;
             if (inst_bytes <= cap) {
                 int per = static_cast<int>(std::min<int64_t>(n_inst, 1));
-                while (per < n_inst && batch_bytes(2 * P.n_hbm * int64_t{per + 1}, epre[P.n_hbm] * (per + 1), steps) <= cap)
+                while (per < n_inst &&
+                       batch_bytes(2 * P.n_hbm * int64_t{per + 1}, epre[P.n_hbm] * (per + 1), steps, P.n_hbm) <= cap)
                     ++per;
                 for (int b = 0; b < n_inst; b += per) batches.push_back({b, std::min(per, n_inst - b), 0, P.n_hbm});
             } else {
                 for (int b = 0; b < n_inst; ++b)
                     for (int k0 = 0; k0 < P.n_hbm;) {
                         int k1 = k0 + 1;
-                        while (k1 < P.n_hbm && batch_bytes(2 * int64_t{k1 + 1 - k0}, epre[k1 + 1] - epre[k0], steps) <= cap)
+                        while (k1 < P.n_hbm &&
+                               batch_bytes(2 * int64_t{k1 + 1 - k0}, epre[k1 + 1] - epre[k0], steps, k1 + 1 - k0) <= cap)
                             ++k1;
                         batches.push_back({b, 1, k0, k1});
                         k0 = k1;
@@ -525,21 +611,37 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                 bt.nb = R.nb;
                 bt.steps = steps;
                 bt.entry_pre = static_cast<const int64_t *>(p.d_entry_pre) + P.hbm0;
-                bt.block_pre = static_cast<const int64_t *>(p.d_block_pre) + P.hbm0;
                 bt.ents_per_inst = epre[R.k1] - epre[R.k0];
-                bt.blks_per_inst = bpre[R.k1] - bpre[R.k0];
                 const int64_t nt = static_cast<int64_t>(R.nb) * (R.k1 - R.k0) * 2;
-                bt.emax = reinterpret_cast<int32_t *>(heavy);
-                bt.es = reinterpret_cast<int32_t *>(heavy + align256(nt * steps * 4));
-                bt.tables = heavy + align256(nt * steps * 4) + align256(nt * 4);
+                char *q = heavy;
+                bt.tabs = reinterpret_cast<TnTab *>(q);
+                q += align256(nt * static_cast<int64_t>(sizeof(TnTab)));
+                bt.desc = reinterpret_cast<TnDescX *>(q);
+                q += align256(nt * steps * static_cast<int64_t>(sizeof(TnDescX)));
+                bt.blkpre = reinterpret_cast<int32_t *>(q);
+                q += align256(static_cast<int64_t>(steps) * (R.k1 - R.k0 + 1) * 4);
+                bt.emax = reinterpret_cast<int32_t *>(q);
+                q += align256(nt * steps * 4);
+                bt.es = reinterpret_cast<int32_t *>(q);
+                q += align256(nt * 4);
+                bt.tables = q;
                 int max_steps = 0;
                 for (int k = R.k0; k < R.k1; ++k)
                     max_steps = std::max(max_steps, p.shapes[p.items[bt.item_hbm0 + k].shape].n_steps);
-                hipLaunchKernelGGL(k_tn_hbm_prep<TROP>, dim3(static_cast<uint32_t>((nt + 63) / 64)), dim3(64), 0, st,
+                hipLaunchKernelGGL(k_tn_hbm_prep, dim3(static_cast<uint32_t>((nt * steps + 255) / 256)), dim3(256), 0, st,
                                    jb, bt);
-                const dim3 grid(static_cast<uint32_t>(R.nb * bt.blks_per_inst));
-                for (int t = 0; t < max_steps; ++t)
-                    hipLaunchKernelGGL(k_tn_hbm_step<TROP>, grid, dim3(kTnThreads), 0, st, jb, bt, wt, t);
+                hipLaunchKernelGGL(k_tn_hbm_blocks, dim3(static_cast<uint32_t>((steps + 63) / 64)), dim3(64), 0, st, jb, bt);
+                for (int t = 0; t < max_steps; ++t) {
+                    // work groups of one (instance, value) at this step: as k_tn_hbm_blocks
+                    int64_t blocks_t = 0;
+                    for (int k = R.k0; k < R.k1; ++k) {
+                        const TnShape &sh = p.shapes[p.items[bt.item_hbm0 + k].shape];
+                        if (t < sh.n_steps) blocks_t += tn_table_blocks(p.steps[sh.step0 + t].n_base);
+                    }
+                    if (blocks_t == 0) continue;
+                    hipLaunchKernelGGL(k_tn_hbm_step<TROP>, dim3(static_cast<uint32_t>(int64_t{R.nb} * 2 * blocks_t)),
+                                       dim3(kTnThreads), 0, st, bt, wt, t, static_cast<int>(blocks_t));
+                }
                 hipLaunchKernelGGL(k_tn_hbm_final<TROP>, dim3(static_cast<uint32_t>((nt + 63) / 64)), dim3(64), 0,
                                    st, jb, bt);
             }
@@ -575,10 +677,10 @@ int64_t sg_tn_workspace_bytes(const sg_tn_plan *p, int32_t n_inst, int32_t full)
         if (!P.n_hbm) continue;
         const int64_t *epre = p->hbm_entry_pre.data() + P.hbm0;
         if (full) {
-            heavy = std::max(heavy, batch_bytes(int64_t{2} * P.n_hbm * n_inst, epre[P.n_hbm] * n_inst, P.hbm_steps));
+            heavy = std::max(heavy, batch_bytes(int64_t{2} * P.n_hbm * n_inst, epre[P.n_hbm] * n_inst, P.hbm_steps, P.n_hbm));
         } else {
             for (int k = 0; k < P.n_hbm; ++k)
-                heavy = std::max(heavy, batch_bytes(2, epre[k + 1] - epre[k], P.hbm_steps));
+                heavy = std::max(heavy, batch_bytes(2, epre[k + 1] - epre[k], P.hbm_steps, 1));
         }
     }
     return res_bytes(*p, n_inst) + heavy;
@@ -588,7 +690,7 @@ int sg_tn_plan_destroy(sg_tn_plan *p)
 {
     if (!p) return fail(SG_EINVAL, "sg_tn_plan_destroy: NULL plan");
     clear_error();
-    for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre, p->d_block_pre})
+    for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre})
         if (d) (void)hipFree(d);
     delete p;
     return SG_OK;

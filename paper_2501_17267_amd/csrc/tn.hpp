@@ -29,21 +29,33 @@ constexpr int8_t kTnConst = -1;    // fixed (decimated earlier) neighbour
 constexpr int8_t kTnCentre = -2;   // the centre
 constexpr int8_t kTnNone = -3;     // outside the fragment or already eliminated
 
+// The workspace tier updates only "canonical" entries, those whose bits
+// of free slots are 0 (the other entries are copies of them).  Before step t
+// the canonical bits are the slots P active after step t-1.  The step reads,
+// for every assignment of P minus the eliminated slot a, the entries with
+// a = 0 and a = 1 (one entry when v only now takes its slot: the table is
+// constant along a), and writes every combination of the slots that become
+// active at this step ("new", a excluded), with a = 0.  No thread reads a
+// location another thread writes, so the update is in place.
 struct TnStep {
     int16_t lv;        // local index of the eliminated spin, lx + l (ly + l lz)
     uint8_t a;         // its slot
-    uint8_t pad;
+    uint8_t a_active;  // 1 when slot a was already active before the step
     int8_t code[6];    // per direction +x,-x,+y,-y,+z,-z: slot (>= 0) or kTn*
-    int16_t pad2;
+    uint8_t n_runs;    // canonical bits other than a as runs of consecutive slots
+    uint8_t n_base;    //   and their count
+    uint32_t newmask;  // slots that become active at this step, a excluded
+    uint8_t run_start[8];
+    uint8_t run_len[8];
 };
-static_assert(sizeof(TnStep) == 12, "TnStep layout");
+static_assert(sizeof(TnStep) == 32, "TnStep layout");
 
 struct TnShape {
     int32_t W;         // table bits (2^W entries)
     int32_t n_steps;   // eliminations
     int32_t step0;     // first step in the step array
     int8_t ccode[6];   // the centre's neighbours: kTnConst (fixed) or kTnNone
-    int16_t pad;
+    int16_t max_base;  // most canonical read bits of a step (workspace tier)
 };
 static_assert(sizeof(TnShape) == 20, "TnShape layout");
 
@@ -70,17 +82,16 @@ struct sg_tn_plan {
     std::vector<sg::TnStep> steps;
     std::vector<sg::TnItem> items;
     std::vector<sg::TnPhase> phases;
-    // workspace items in phase order: table-entry and block prefixes of one
-    // instance (both centre values), per phase relative to the phase start
+    // workspace items in phase order: table-entry prefix of one instance
+    // (both centre values), per phase relative to the phase start
     std::vector<int64_t> hbm_entry_pre;   // [n_hbm_total + n_phases]
-    std::vector<int64_t> hbm_block_pre;
     int32_t max_bits = 0, max_steps = 0, n_lds = 0, n_hbm = 0, max_items = 0;
     double pair_updates = 0;
     // device copies (first decimation)
     std::mutex mu;
     int device = -1;
     void *d_shapes = nullptr, *d_steps = nullptr, *d_items = nullptr;
-    void *d_entry_pre = nullptr, *d_block_pre = nullptr;
+    void *d_entry_pre = nullptr;
 };
 
 namespace sg {
@@ -88,12 +99,13 @@ namespace sg {
 constexpr int kTnThreads = 256;
 constexpr int kTnPairsPerThread = 4;   // workspace tables: pair updates per thread and step
 
-// work groups of one workspace table of 2^W entries in a step launch
-inline int64_t tn_table_blocks(int W)
+// work groups per workspace table in a step launch: enough for 2^n_base
+// canonical reads, kTnPairsPerThread per thread
+inline int64_t tn_table_blocks(int n_base)
 {
-    const int64_t pairs = W > 0 ? (int64_t{1} << (W - 1)) : 1;
+    const int64_t items = int64_t{1} << n_base;
     constexpr int64_t per = int64_t{kTnThreads} * kTnPairsPerThread;
-    return (pairs + per - 1) / per;
+    return (items + per - 1) / per;
 }
 
 int tn_phase_of(int order, int L, int h, int x, int y, int z);

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <stdexcept>
 #include <numeric>
 
 #include "common.hpp"
@@ -168,7 +169,8 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
         used |= uint64_t{1} << s;
         return s;
     };
-    int W = 0;
+    int W = 0, max_base = 0;
+    uint64_t P = 0;   // canonical (active) slots before the step
     for (int v : order) {
         if (slot[v] < 0) slot[v] = take();
         TnStep st{};
@@ -194,11 +196,38 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
                 W = std::max(W, s + 1);
                 break;
             }
+        // canonical bookkeeping of the workspace tier: the slots active now
+        // are exactly `used`; those not in P are new at this step
+        const uint64_t abit = uint64_t{1} << st.a;
+        const uint64_t fresh = used & ~P;
+        const uint64_t base = P & ~abit;
+        st.a_active = (P & abit) ? 1 : 0;
+        st.newmask = static_cast<uint32_t>(fresh & ~abit);
+        int n_runs = 0, n_base = 0;
+        for (int b = 0; b < 64;) {
+            if (!((base >> b) & 1u)) {
+                ++b;
+                continue;
+            }
+            int e = b;
+            while (e < 64 && ((base >> e) & 1u)) ++e;
+            if (n_runs == 8) throw std::length_error("more than 8 runs");
+            st.run_start[n_runs] = static_cast<uint8_t>(b);
+            st.run_len[n_runs] = static_cast<uint8_t>(e - b);
+            ++n_runs;
+            n_base += e - b;
+            b = e;
+        }
+        st.n_runs = static_cast<uint8_t>(n_runs);
+        st.n_base = static_cast<uint8_t>(n_base);
+        max_base = std::max(max_base, n_base);
         used &= ~(uint64_t{1} << slot[v]);
+        P = used;
         done[v] = 1;
         steps.push_back(st);
     }
     sh.W = W;
+    sh.max_base = static_cast<int16_t>(max_base);
     return sh;
 }
 
@@ -291,16 +320,12 @@ int sg_tn_plan_create(int32_t L, int32_t halo, int32_t order, int32_t lds_max_bi
                 }
             }
             P.hbm0 = static_cast<int64_t>(p->hbm_entry_pre.size());
-            int64_t e = 0, b = 0;
+            int64_t e = 0;
             p->hbm_entry_pre.push_back(0);
-            p->hbm_block_pre.push_back(0);
             for (const TnItem &it : hbm) {
                 p->items.push_back(it);
-                const int W = p->shapes[it.shape].W;
-                e += 2 * (int64_t{1} << W);
-                b += 2 * tn_table_blocks(W);
+                e += 2 * (int64_t{1} << p->shapes[it.shape].W);
                 p->hbm_entry_pre.push_back(e);
-                p->hbm_block_pre.push_back(b);
             }
             P.n_hbm = static_cast<int32_t>(hbm.size());
             p->n_lds += P.n_lds;
@@ -310,6 +335,9 @@ int sg_tn_plan_create(int32_t L, int32_t halo, int32_t order, int32_t lds_max_bi
     } catch (const std::bad_alloc &) {
         delete p;
         return fail(SG_ENOMEM, "sg_tn_plan_create: host allocation");
+    } catch (const std::length_error &) {
+        delete p;
+        return fail(SG_EUNSUPPORTED, "sg_tn_plan_create: an elimination step needs more than 8 slot runs");
     }
     *out = p;
     return SG_OK;
@@ -333,7 +361,7 @@ int sg_tn_plan_info_get(const sg_tn_plan *p, sg_tn_plan_info *out)
     return SG_OK;
 }
 
-int sg_tn_plan_program(const sg_tn_plan *p, int32_t *n_shapes, int32_t *shapes, int32_t *n_steps, int16_t *steps,
+int sg_tn_plan_program(const sg_tn_plan *p, int32_t *n_shapes, int32_t *shapes, int32_t *n_steps, int32_t *steps,
                        int32_t *n_items, int32_t *items)
 {
     if (!p || !n_shapes || !n_steps || !n_items) return fail(SG_EINVAL, "sg_tn_plan_program: NULL pointer");
@@ -354,9 +382,23 @@ int sg_tn_plan_program(const sg_tn_plan *p, int32_t *n_shapes, int32_t *shapes, 
     if (steps)
         for (size_t i = 0; i < p->steps.size(); ++i) {
             const TnStep &s = p->steps[i];
-            steps[8 * i + 0] = s.lv;
-            steps[8 * i + 1] = s.a;
-            for (int d = 0; d < 6; ++d) steps[8 * i + 2 + d] = s.code[d];
+            int32_t *row = steps + 16 * i;
+            row[0] = s.lv;
+            row[1] = s.a;
+            for (int d = 0; d < 6; ++d) row[2 + d] = s.code[d];
+            row[8] = s.a_active;
+            row[9] = s.n_runs;
+            row[10] = s.n_base;
+            row[11] = static_cast<int32_t>(s.newmask);
+            for (int q = 0; q < 2; ++q) {
+                uint32_t st = 0, ln = 0;
+                for (int b = 0; b < 4; ++b) {
+                    st |= static_cast<uint32_t>(s.run_start[4 * q + b]) << (8 * b);
+                    ln |= static_cast<uint32_t>(s.run_len[4 * q + b]) << (8 * b);
+                }
+                row[12 + q] = static_cast<int32_t>(st);
+                row[14 + q] = static_cast<int32_t>(ln);
+            }
         }
     if (items)
         for (size_t i = 0; i < p->items.size(); ++i) {

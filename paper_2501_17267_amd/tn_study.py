@@ -1,0 +1,101 @@
+"""The paper's own form of the meta-heuristic (Sec. II, App. B, C): the
+tensor-network subsystem optimiser (exact l^3 fragment marginals, beta = 2)
+on tile-planted stand-in instances.
+
+eps_lin(L)  20 instances per L, l = 5, beta = 2, wavefront order: mean and
+            largest eps, the fit a/L + b (Sec. II), the time per instance
+            alone and in a 20-instance call, and the table pair updates per
+            second; the tropical (zero-temperature) form beside it.
+beta study  App. C: mean eps versus beta at one size.
+l study     App. B: mean eps versus the fragment edge at L = 20 (l = 3, 5;
+            single-spin fragments are centred, so l is odd here).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import TnPlan, make_instance, tn_decimate
+from . import workloads as wl
+
+
+def _batch(torch, L, n):
+    specs = wl.tn_instances(L, n)
+    Js, egs = [], []
+    for s in specs:
+        J, _, e = make_instance(L, s.cls, s.seed)
+        Js.append(np.asarray(J).reshape(6, L ** 3))
+        egs.append(e)
+    return torch.from_numpy(np.stack(Js)).cuda(), np.array(egs, np.int64)
+
+
+def _eps(en, egs):
+    e = en.cpu().numpy().astype(np.int64)
+    return (e - egs) / np.abs(egs)
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) * 1e3
+
+
+def run(torch, sizes=(8, 12, 16, 20, 24, 32), n_inst=20, beta=2.0, beta_L=12,
+        betas=(0.5, 1.0, 2.0, 3.0, 5.0, 8.0), log=print):
+    out = {"sizes": list(sizes), "n_inst": n_inst, "beta": beta, "halo": 2, "order": 1, "per_L": {}}
+    for L in sizes:
+        plan = TnPlan(L, 2, 1)
+        info = plan.info()
+        J, egs = _batch(torch, L, n_inst)
+        ws = torch.empty((plan.workspace_bytes(n_inst, True) + 7) // 8, dtype=torch.float64, device="cuda")
+        tn_decimate(plan, J[:1], beta, workspace=ws, want_score=False)          # warm-up
+        (sp, en, _), ms1 = _timed(torch, lambda: tn_decimate(plan, J[:1], beta, workspace=ws, want_score=False))
+        (sp, en, _), msb = _timed(torch, lambda: tn_decimate(plan, J, beta, workspace=ws, want_score=False))
+        eps = _eps(en, egs)
+        (_, ent, _), mst = _timed(torch, lambda: tn_decimate(plan, J, 0.0, True, workspace=ws, want_score=False))
+        epst = _eps(ent, egs)
+        row = {"N": L ** 3, "eps_mean": float(eps.mean()), "eps_max": float(eps.max()),
+               "frac_exact": float(np.mean(eps == 0.0)),
+               "ms_single": ms1, "ms_per_instance_batched": msb / n_inst,
+               "pair_updates_per_instance": info["pair_updates"],
+               "pair_updates_per_s_batched": info["pair_updates"] * n_inst / (msb * 1e-3),
+               "lds_sites": info["n_lds_sites"], "hbm_sites": info["n_hbm_sites"], "max_bits": info["max_bits"],
+               "tropical_eps_mean": float(epst.mean()), "tropical_ms_per_instance_batched": mst / n_inst}
+        log(f"tn L={L}: {row}")
+        out["per_L"][str(L)] = row
+        del ws
+        plan.close()
+    Ls = np.array(sorted(int(L) for L in out["per_L"]), np.float64)
+    if len(Ls) >= 3:
+        em = np.array([out["per_L"][str(int(L))]["eps_mean"] for L in Ls])
+        A = np.stack([1.0 / Ls, np.ones_like(Ls)], axis=1)
+        (a, b), *_ = np.linalg.lstsq(A, em, rcond=None)
+        out["fit_eps_a_over_L_plus_b"] = {"a": float(a), "b": float(b)}
+        T = np.array([out["per_L"][str(int(L))]["ms_per_instance_batched"] for L in Ls])
+        sel = Ls >= 16
+        if sel.sum() >= 2:
+            out["time_alpha_batched_L_ge_16"] = float(np.polyfit(np.log(Ls[sel] ** 3), np.log(T[sel]), 1)[0])
+    # App. C: eps versus beta
+    plan = TnPlan(beta_L, 2, 1)
+    J, egs = _batch(torch, beta_L, n_inst)
+    ws = torch.empty((plan.workspace_bytes(n_inst, True) + 7) // 8, dtype=torch.float64, device="cuda")
+    out["beta_study"] = {"L": beta_L, "rows": []}
+    for b in betas:
+        _, en, _ = tn_decimate(plan, J, b, workspace=ws, want_score=False)
+        e = _eps(en, egs)
+        out["beta_study"]["rows"].append({"beta": b, "eps_mean": float(e.mean()), "eps_max": float(e.max())})
+        log(f"tn beta={b} L={beta_L}: eps_mean {e.mean():.5f}")
+    # App. B: eps versus the fragment edge
+    out["l_study"] = {"L": 20, "rows": []}
+    J, egs = _batch(torch, 20, n_inst)
+    for h in (1, 2):
+        p = TnPlan(20, h, 1)
+        w = torch.empty((p.workspace_bytes(n_inst, True) + 7) // 8, dtype=torch.float64, device="cuda")
+        _, en, _ = tn_decimate(p, J, beta, workspace=w, want_score=False)
+        e = _eps(en, egs)
+        out["l_study"]["rows"].append({"l": 2 * h + 1, "eps_mean": float(e.mean()), "eps_max": float(e.max())})
+        log(f"tn l={2 * h + 1} L=20: eps_mean {e.mean():.5f}")
+    return out

@@ -24,7 +24,7 @@ MASTER_SEED = 0x250117267
 MASK64 = (1 << 64) - 1
 T6 = 6  # class code: number of frustrated faces per tile
 
-WORKLOAD_IDS = {"sa_small": 1, "sa_batch": 2, "pt": 3, "uneven": 4, "serve": 5, "fragment": 6}
+WORKLOAD_IDS = {"sa_small": 1, "sa_batch": 2, "pt": 3, "uneven": 4, "serve": 5, "fragment": 6, "tn": 7}
 
 
 def mix64(x: int) -> int:
@@ -142,3 +142,9 @@ def fragment_settings():
 
 def fragment_instances(L: int, n: int = 20):
     return tuple(InstanceSpec(L, instance_seed("fragment", 1000 * L + k), k) for k in range(n))
+
+
+def tn_instances(L: int, n: int = 20):
+    """Instances of the tensor-network meta-heuristic study (one decimation
+    each, deterministic: no counter words)."""
+    return tuple(InstanceSpec(L, instance_seed("tn", 1000 * L + k), k) for k in range(n))

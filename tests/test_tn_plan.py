@@ -31,7 +31,7 @@ def _execute(L, h, J, dec, site, shape, steps, beta, tropical, sc):
     log = 0.0
     idx = np.arange(1 << W, dtype=np.int64)
     for t in range(ns):
-        lv, a, *codes = (int(v) for v in steps[s0 + t])
+        lv, a, *codes = (int(v) for v in steps[s0 + t][:8])
         g = _wrap(L, site, lv % l - h, (lv // l) % l - h, lv // (l * l) - h)
         hc, act = 0, []
         for d, code in enumerate(codes):
@@ -65,6 +65,71 @@ def _execute(L, h, J, dec, site, shape, steps, beta, tropical, sc):
     return int(T[0]) + es if tropical else log + math.log(T[0]) - beta * es
 
 
+def _execute_canonical(L, h, J, dec, site, shape, steps, beta, tropical, sc):
+    """The same table by the workspace tier's rule: only canonical entries
+    (free-slot bits 0) are read and written; each read pair (a = 0, 1, or
+    one entry when slot a is new) writes every combination of the new slots."""
+    W, ns, s0, cmask = (int(v) for v in shape)
+    l = 2 * h + 1
+    T = np.full(1 << W, -(1 << 40), np.int64) if tropical else np.full(1 << W, np.nan)
+    T[0] = 0 if tropical else 1.0          # a fragment without free spins
+    log = 0.0
+    P = 0
+    for t in range(ns):
+        row = [int(v) for v in steps[s0 + t]]
+        lv, a, codes = row[0], row[1], row[2:8]
+        a_active, n_runs, n_base, newmask = row[8], row[9], row[10], row[11] & 0xFFFFFFFF
+        starts = [(row[12 + r // 4] >> (8 * (r % 4))) & 0xFF for r in range(n_runs)]
+        lens = [(row[14 + r // 4] >> (8 * (r % 4))) & 0xFF for r in range(n_runs)]
+        assert a_active == ((P >> a) & 1) and sum(lens) == n_base
+        assert (newmask & P) == 0 and not (newmask >> a) & 1
+        base = P & ~(1 << a)
+        assert sum(1 << (st + k) for st, ln in zip(starts, lens) for k in range(ln)) == base
+        g = _wrap(L, site, lv % l - h, (lv // l) % l - h, lv // (l * l) - h)
+        hc, act = 0, []
+        for d, code in enumerate(codes):
+            if code == -3:
+                continue
+            Jd = int(J[d, g])
+            if code >= 0:
+                assert ((P | newmask | (1 << a)) >> code) & 1
+                act.append((Jd, code))
+            elif code == -1:
+                hc += Jd * int(dec[_wrap(L, g, *_DIRS[d])])
+            else:
+                hc += Jd * sc
+        outs = {}
+        for p in range(1 << n_base):
+            I, used = 0, 0
+            for st, ln in zip(starts, lens):
+                I |= ((p >> used) & ((1 << ln) - 1)) << st
+                used += ln
+            if t == 0:
+                t0 = t1 = 0 if tropical else 1.0
+            else:
+                t0 = T[I]
+                t1 = T[I | (1 << a)] if a_active else t0
+                assert (tropical and t0 != -(1 << 40)) or (not tropical and not np.isnan(t0))
+            c = 0
+            while True:
+                O = I | c
+                hh = hc + sum(Jd * (1 - 2 * ((O >> b) & 1)) for Jd, b in act)
+                outs[O] = min(t0 + hh, t1 - hh) if tropical else t0 * math.exp(-beta * hh) + t1 * math.exp(beta * hh)
+                c = (c - newmask) & newmask
+                if c == 0:
+                    break
+        if not tropical:
+            m = max(outs.values())
+            log += math.log(m)
+            outs = {k: v / m for k, v in outs.items()}
+        for O, v in outs.items():
+            T[O] = v
+        P = (P | newmask | (1 << a)) & ~(1 << a)
+    assert P == 0
+    es = sum(int(J[d, site]) * int(dec[_wrap(L, site, *_DIRS[d])]) for d in range(6) if (cmask >> d) & 1) * sc
+    return int(T[0]) + es if tropical else log + math.log(T[0]) - beta * es
+
+
 def _check_plan(L, h, order, n_sample=None, tropical=False, max_bits=None, seed=0):
     plan = sg.TnPlan(L, h, order)
     shapes, steps, items = plan.program()
@@ -92,7 +157,14 @@ def _check_plan(L, h, order, n_sample=None, tropical=False, max_bits=None, seed=
         zp = _execute(L, h, J, dec, site, shapes[shape_of[site]], steps, 2.0, tropical, 1)
         zm = _execute(L, h, J, dec, site, shapes[shape_of[site]], steps, 2.0, tropical, -1)
         got = (zm - zp) if tropical else (zp - zm)
+        cp = _execute_canonical(L, h, J, dec, site, shapes[shape_of[site]], steps, 2.0, tropical, 1)
+        cm = _execute_canonical(L, h, J, dec, site, shapes[shape_of[site]], steps, 2.0, tropical, -1)
+        got_c = (cm - cp) if tropical else (cp - cm)
         ref = tn.site_score(L, J, dec, site, h, 2.0, tropical)
+        if tropical:
+            assert got_c == ref, (site, got_c, ref)
+        else:
+            assert abs(got_c - ref) <= 1e-9 * max(1.0, abs(ref)), (site, got_c, ref)
         if tropical:
             assert got == ref, (site, got, ref)
         else:
