@@ -191,7 +191,7 @@ def cpu_baseline_fragment(sg, wl, L=12):
             "sample": f"{cores} instances at L={L}, one per thread, {dt:.1f} s"}
 
 
-def cpu_baseline_tn(sg, wl, L=20, n_sites=48):
+def cpu_baseline_tn(sg, wl, L=20, n_sites=960):
     """The oracle's exact fragment marginals (l = 5, beta = 2) for a sample
     of sites of the first L = 20 instance: random sites whose tables fit the
     LDS tier (the oracle's elimination order makes the larger ones take
