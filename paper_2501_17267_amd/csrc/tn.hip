@@ -358,11 +358,17 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     using T = typename std::conditional<TROP, int32_t, double>::type;
     __shared__ double w[kTnWeights];
     __shared__ int s_emax[kTnThreads / 64];
+    __shared__ int32_t pre[kTnThreads + 1];
     const int tid = static_cast<int>(threadIdx.x);
     const int nk = bt.k1 - bt.k0;
     const int64_t g = static_cast<int64_t>(blockIdx.x) / blocks_t;   // (instance, value)
     const int rb = static_cast<int>(static_cast<int64_t>(blockIdx.x) - g * blocks_t);
-    const int32_t *pre = bt.blkpre + static_cast<int64_t>(t) * (nk + 1);
+    // the step's prefix row, staged in LDS (batches have at most kTnThreads items)
+    const int32_t *row = bt.blkpre + static_cast<int64_t>(t) * (nk + 1);
+    for (int i = tid; i <= nk; i += kTnThreads) pre[i] = row[i];
+    if (!TROP)
+        for (int i = tid; i < kTnWeights; i += kTnThreads) w[i] = wt.w[i];
+    __syncthreads();
     int lo = 0, hi = nk - 1;   // the item: last kk with pre[kk] <= rb
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -377,10 +383,6 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     const TnTab tb = bt.tabs[tix];
     const TnDescX x = bt.desc[tix * bt.steps + t];
     T *tab = reinterpret_cast<T *>(bt.tables) + tb.off;
-    if (!TROP) {
-        for (int i = tid; i < kTnWeights; i += kTnThreads) w[i] = wt.w[i];
-        __syncthreads();
-    }
     const double scale = (!TROP && t > 0) ? ldexp(1.0, -bt.emax[tix * bt.steps + t - 1]) : 1.0;
     const int64_t items = int64_t{1} << x.n_base;
     const int64_t stride = static_cast<int64_t>(bpt) * kTnThreads;
@@ -588,12 +590,14 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                 while (per < n_inst &&
                        batch_bytes(2 * P.n_hbm * int64_t{per + 1}, epre[P.n_hbm] * (per + 1), steps, P.n_hbm) <= cap)
                     ++per;
-                for (int b = 0; b < n_inst; b += per) batches.push_back({b, std::min(per, n_inst - b), 0, P.n_hbm});
+                for (int b = 0; b < n_inst; b += per)
+                    for (int k0 = 0; k0 < P.n_hbm; k0 += kTnThreads)
+                        batches.push_back({b, std::min(per, n_inst - b), k0, std::min(P.n_hbm, k0 + kTnThreads)});
             } else {
                 for (int b = 0; b < n_inst; ++b)
                     for (int k0 = 0; k0 < P.n_hbm;) {
                         int k1 = k0 + 1;
-                        while (k1 < P.n_hbm &&
+                        while (k1 < P.n_hbm && k1 - k0 < kTnThreads &&
                                batch_bytes(2 * int64_t{k1 + 1 - k0}, epre[k1 + 1] - epre[k0], steps, k1 + 1 - k0) <= cap)
                             ++k1;
                         batches.push_back({b, 1, k0, k1});
