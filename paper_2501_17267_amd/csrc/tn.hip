@@ -116,6 +116,15 @@ __device__ inline int tn_centre_energy(const TnJob &jb, const int8_t *J, const i
     return e * sc;
 }
 
+// field without the clamp (the canonical-slot part of a split field)
+__device__ inline int tn_field_raw(const TnDesc &D, uint32_t I0)
+{
+    int hh = D.hc;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) hh += D.J[d] * (1 - 2 * static_cast<int>((I0 >> ((D.slots >> (5 * d)) & 31u)) & 1u));
+    return hh;
+}
+
 __device__ inline int tn_field(const TnDesc &D, uint32_t I0)
 {
     int hh = D.hc;
@@ -359,6 +368,7 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     __shared__ double w[kTnWeights];
     __shared__ int s_emax[kTnThreads / 64];
     __shared__ int32_t pre[kTnThreads + 1];
+    __shared__ int32_t s_hn[64];   // field from the new slots, per combination
     const int tid = static_cast<int>(threadIdx.x);
     const int nk = bt.k1 - bt.k0;
     const int64_t g = static_cast<int64_t>(blockIdx.x) / blocks_t;   // (instance, value)
@@ -388,38 +398,67 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     const int64_t stride = static_cast<int64_t>(bpt) * kTnThreads;
     const uint32_t abit = 1u << x.d.a;
     const uint32_t nm = x.newmask;
-    // all reads first (several in flight per thread), then the updates
-    uint32_t I[kTnPairsPerThread];
-    T t0[kTnPairsPerThread], t1[kTnPairsPerThread];
+    // the field splits into the part from canonical slots (once per read) and
+    // the part from the new slots (per combination, from s_hn)
+    TnDesc db = x.d;
+    int n_new = 0;
 #pragma unroll
-    for (int r = 0; r < kTnPairsPerThread; ++r) {
-        const int64_t p = tblk * kTnThreads + tid + r * stride;
-        I[r] = tn_deposit(static_cast<uint32_t>(p), x);
-        t0[r] = t1[r] = TROP ? T(0) : T(1);
-        if (p < items && t > 0) {
-            t0[r] = tab[I[r]];
-            t1[r] = x.a_active ? tab[I[r] | abit] : t0[r];
-        }
-    }
-    double m = 0.0;
-#pragma unroll
-    for (int r = 0; r < kTnPairsPerThread; ++r) {
-        const int64_t p = tblk * kTnThreads + tid + r * stride;
-        if (p >= items) break;
+    for (int d = 0; d < 6; ++d)
+        if ((nm >> ((db.slots >> (5 * d)) & 31u)) & 1u) db.J[d] = 0;
+    for (uint32_t b = nm; b; b &= b - 1) ++n_new;
+    if (tid < (1 << n_new)) {
+        // combination tid: the bits of tid deposited into the new slots, the
+        // tid-th subset in increasing order, as the update loop visits them
         uint32_t c = 0;
-        do {
-            const uint32_t O = I[r] | c;
-            const int hh = tn_field(x.d, O);
-            T v;
-            if (TROP) {
-                v = min(t0[r] + hh, t1[r] - hh);
-            } else {
-                v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
-                m = fmax(m, static_cast<double>(v));
+        int used = 0;
+        for (int b = 0; b < 32; ++b)
+            if ((nm >> b) & 1u) c |= ((static_cast<uint32_t>(tid) >> used++) & 1u) << b;
+        int hn = 0;
+        for (int d = 0; d < 6; ++d) {
+            const uint32_t sl = (x.d.slots >> (5 * d)) & 31u;
+            if ((nm >> sl) & 1u) hn += x.d.J[d] * (1 - 2 * static_cast<int>((c >> sl) & 1u));
+        }
+        s_hn[tid] = hn;
+    }
+    __syncthreads();
+    // rounds of kTnReadsInFlight reads (all issued before any update), up to
+    // kTnPairsPerThread reads per thread
+    double m = 0.0;
+    for (int r0 = 0; r0 < kTnPairsPerThread; r0 += kTnReadsInFlight) {
+        if (tblk * kTnThreads + r0 * stride >= items) break;   // uniform over the work group
+        uint32_t I[kTnReadsInFlight];
+        T t0[kTnReadsInFlight], t1[kTnReadsInFlight];
+#pragma unroll
+        for (int r = 0; r < kTnReadsInFlight; ++r) {
+            const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
+            I[r] = tn_deposit(static_cast<uint32_t>(p), x);
+            t0[r] = t1[r] = TROP ? T(0) : T(1);
+            if (p < items && t > 0) {
+                t0[r] = tab[I[r]];
+                t1[r] = x.a_active ? tab[I[r] | abit] : t0[r];
             }
-            tab[O] = v;
-            c = (c - nm) & nm;
-        } while (c != 0);
+        }
+#pragma unroll
+        for (int r = 0; r < kTnReadsInFlight; ++r) {
+            const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
+            if (p >= items) break;
+            const int hb = tn_field_raw(db, I[r]);
+            uint32_t c = 0;
+            int kc = 0;
+            do {
+                const uint32_t O = I[r] | c;
+                const int hh = min(max(hb + s_hn[kc++], -kTnHMax), kTnHMax);
+                T v;
+                if (TROP) {
+                    v = min(t0[r] + hh, t1[r] - hh);
+                } else {
+                    v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
+                    m = fmax(m, static_cast<double>(v));
+                }
+                tab[O] = v;
+                c = (c - nm) & nm;
+            } while (c != 0);
+        }
     }
     if (!TROP) {
         const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);

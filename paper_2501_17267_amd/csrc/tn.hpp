@@ -97,7 +97,8 @@ struct sg_tn_plan {
 namespace sg {
 
 constexpr int kTnThreads = 256;
-constexpr int kTnPairsPerThread = 4;   // workspace tables: pair updates per thread and step
+constexpr int kTnReadsInFlight = 4;    // workspace tables: canonical reads a thread issues at once
+constexpr int kTnPairsPerThread = 4;   //   and reads per thread and step (in rounds of the above)
 
 // work groups per workspace table in a step launch: enough for 2^n_base
 // canonical reads, kTnPairsPerThread per thread
