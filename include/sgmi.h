@@ -226,8 +226,9 @@ int sg_pticm_run(const sg_instance *inst, const sg_pticm_args *args, const uint3
  * count.  Anneal r starts its free spins from bit 31 of Philox word 0 of
  * (r l^3 + j, 0xFFFFFFFF, k, run) (set: -1) and makes n_sweeps sweeps
  * (colour (x+y+z) mod 2 = 0, then 1) of Metropolis proposals at its free
- * sites with u = Philox word 0 of (r l^3 + j, 2s + colour, k, run) against
- * thr row s (as sa_anneal).  The anneal with the lowest in-fragment energy
+ * sites with u = Philox word s mod 4 of (r l^3 + j, 2 floor(s/4) + colour,
+ * k, run) (one call serves a site's four sweeps 4m..4m+3) against thr row s
+ * (as sa_anneal).  The anneal with the lowest in-fragment energy
  * (lowest r among equals) gives the core's spins.  The time is linear in
  * N: N/c^3 fragments of fixed cost. */
 #define SG_FRAG_MAX_L 9      /* largest fragment edge l */

@@ -560,7 +560,7 @@ static int frag_params_ok(int L, int c, int h, int order)
     return order != 0 || nb % P == 0;
 }
 
-static uint32_t frag_word0(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+static uint32_t frag_word(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int w)
 {
     uint32_t ctr[4], out[4];
     ctr[0] = c0;
@@ -568,7 +568,7 @@ static uint32_t frag_word0(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
     ctr[2] = c2;
     ctr[3] = c3;
     orc_philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
-    return out[0];
+    return out[w];
 }
 
 int orc_frag_anneal(int L, const int8_t *J, int core, int halo, int64_t k, int rep, uint64_t seed,
@@ -602,7 +602,7 @@ int orc_frag_anneal(int L, const int8_t *J, int core, int halo, int64_t k, int r
                 if (fixed[j])
                     frag[j] = dec[g[j]];
                 else
-                    frag[j] = (frag_word0(seed, w0 + (uint32_t)j, 0xFFFFFFFFu, (uint32_t)k, run) >> 31) ? -1 : 1;
+                    frag[j] = (frag_word(seed, w0 + (uint32_t)j, 0xFFFFFFFFu, (uint32_t)k, run, 0) >> 31) ? -1 : 1;
             }
     /* sweeps over the free sites, colour by colour */
     for (s = 0; s < S; ++s)
@@ -626,8 +626,9 @@ int orc_frag_anneal(int L, const int8_t *J, int core, int halo, int64_t k, int r
                 if (kk <= 0)
                     acc = 1;
                 else
-                    acc = kk <= K && frag_word0(seed, w0 + (uint32_t)j, (uint32_t)(2 * s + col), (uint32_t)k,
-                                                run) < thr[(int64_t)s * K + (kk - 1)];
+                    /* sweeps 4m..4m+3 of a site use words 0..3 of one call */
+                    acc = kk <= K && frag_word(seed, w0 + (uint32_t)j, (uint32_t)(2 * (s / 4) + col), (uint32_t)k, run,
+                                               s % 4) < thr[(int64_t)s * K + (kk - 1)];
                 if (acc) frag[j] = (int8_t)(-frag[j]);
             }
     /* energy of the in-fragment bonds (+x, +y, +z partners inside) */

@@ -189,26 +189,78 @@ __global__ __launch_bounds__(kFragMaxR * 64) void k_frag_phase(FragJob job, int 
     int8_t *sp = s_spin[r];
     uint32_t *thr_r = s_thr[r];
     const int n0 = s_nsite[0], n01 = s_nsite[1];
-    for (int s = 0; s < job.S; ++s) {
-        if (lane < job.K) thr_r[lane] = job.thr[static_cast<int64_t>(s) * job.K + lane];
-        wave_sync();
-        for (int col = 0; col < 2; ++col) {
-            const int e0 = col ? n0 : 0, e1 = col ? n01 : n0;
-            for (int e = e0 + lane; e < e1; e += 64) {
-                const FragSite fs = s_site[e];
-                const int j = fs.j;
-                int hf = 0;
+    // the first row; each sweep fetches the next row while it runs
+    if (lane < job.K && job.S > 0) thr_r[lane] = job.thr[lane];
+    wave_sync();
+    // The uniforms of site j in sweeps 4m..4m+3 are the four words of one
+    // Philox call with counter (r l^3 + j, 2m + colour, core, run).
+    auto draws = [&](int j, int s, int col) {
+        return philox10(static_cast<uint32_t>(r * n3 + j), 2u * static_cast<uint32_t>(s >> 2) + static_cast<uint32_t>(col),
+                        k, run, job.k0, job.k1);
+    };
+    auto word = [](const Rand4 &u, int i) { return i == 0 ? u.w[0] : i == 1 ? u.w[1] : i == 2 ? u.w[2] : u.w[3]; };
+    // One Metropolis proposal: the site's record and couplings come from fs
+    // and Jd (registers or LDS); u4 holds the site's draws of this block of
+    // four sweeps, or is null to draw them here.
+    auto propose = [&](const FragSite &fs, const int8_t *Jd, int s, int col, const Rand4 *u4) {
+        const int j = fs.j;
+        int hf = 0;
 #pragma unroll
-                for (int d = 0; d < 6; ++d) hf += s_J[d][j] * sp[fs.nb[d]];
-                const int kk = -sp[j] * hf;
-                bool acc = kk <= 0;
-                if (!acc && kk <= job.K) {
-                    const Rand4 u = philox10(static_cast<uint32_t>(r * n3 + j), 2u * static_cast<uint32_t>(s) +
-                                             static_cast<uint32_t>(col), k, run, job.k0, job.k1);
-                    acc = u.w[0] < thr_r[kk - 1];
-                }
-                if (acc) sp[j] = static_cast<int8_t>(-sp[j]);
+        for (int d = 0; d < 6; ++d) hf += Jd[d] * sp[fs.nb[d]];
+        const int kk = -sp[j] * hf;
+        bool acc = kk <= 0;
+        // a zero threshold rejects every draw: no need to draw
+        if (!acc && kk <= job.K && thr_r[kk - 1] != 0u)
+            acc = word(u4 ? *u4 : draws(j, s, col), s & 3) < thr_r[kk - 1];
+        if (acc) sp[j] = static_cast<int8_t>(-sp[j]);
+    };
+    if (n0 <= 64 && n01 - n0 <= 64) {
+        // at most one site per lane and colour (l = 5 single-spin fragments):
+        // each lane keeps its two sites' records and couplings in registers
+        FragSite mine[2];
+        int8_t mj[2][6];
+        bool have[2];
+#pragma unroll
+        for (int col = 0; col < 2; ++col) {
+            const int e = (col ? n0 : 0) + lane;
+            have[col] = e < (col ? n01 : n0);
+            mine[col] = have[col] ? s_site[e] : FragSite{};   // a zeroed record reads site 0
+#pragma unroll
+            for (int d = 0; d < 6; ++d) mj[col][d] = s_J[d][mine[col].j];
+        }
+        Rand4 u4[2] = {};
+        for (int s = 0; s < job.S; ++s) {
+            const uint32_t next = (lane < job.K && s + 1 < job.S)
+                                      ? job.thr[static_cast<int64_t>(s + 1) * job.K + lane] : 0u;
+            if ((s & 3) == 0) {
+#pragma unroll
+                for (int col = 0; col < 2; ++col)
+                    if (have[col]) u4[col] = draws(mine[col].j, s, col);
             }
+#pragma unroll
+            for (int col = 0; col < 2; ++col) {
+                if (have[col]) propose(mine[col], mj[col], s, col, &u4[col]);
+                wave_sync();
+            }
+            if (lane < job.K && s + 1 < job.S) thr_r[lane] = next;
+            wave_sync();
+        }
+    } else {
+        for (int s = 0; s < job.S; ++s) {
+            const uint32_t next = (lane < job.K && s + 1 < job.S)
+                                      ? job.thr[static_cast<int64_t>(s + 1) * job.K + lane] : 0u;
+            for (int col = 0; col < 2; ++col) {
+                const int e0 = col ? n0 : 0, e1 = col ? n01 : n0;
+                for (int e = e0 + lane; e < e1; e += 64) {
+                    const FragSite fs = s_site[e];
+                    int8_t Jd[6];
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) Jd[d] = s_J[d][fs.j];
+                    propose(fs, Jd, s, col, nullptr);
+                }
+                wave_sync();
+            }
+            if (lane < job.K && s + 1 < job.S) thr_r[lane] = next;
             wave_sync();
         }
     }
