@@ -228,6 +228,28 @@ def fragment(a, sg, wl, torch):
     return res
 
 
+def fragment_call(a, sg, wl, torch):
+    """One 20-run decimation call of the measured fragment setting at L = 32
+    (after one warm-up call): the unit the fragment kernel's counters are
+    taken on."""
+    st = wl.fragment_settings()[0]
+    L, n_runs = 32, 20
+    thr = sg.to_device_u32(sg.make_thresholds(sg.make_schedule(0, st.beta0, st.beta1, st.n_sweeps)))
+    spec = wl.fragment_instances(L, 1)[0]
+    inst = sg.Instance.generate(L, spec.seed, spec.chain)
+    seed = wl.philox_seed("fragment")
+    sg.fragment_decimate(inst, thr, st.core, st.halo, st.replicas, st.order, n_runs, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, en = sg.fragment_decimate(inst, thr, st.core, st.halo, st.replicas, st.order, n_runs, seed)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    nominal = n_runs * (L ** 3 // st.core ** 3) * st.replicas * (st.core + 2 * st.halo) ** 3 * st.n_sweeps
+    return {"metric": "ms of one 20-run fragment decimation call (L = 32, l = 5, 8 anneals x 100 sweeps)",
+            "ms": ms, "nominal_proposals_per_s": nominal / (ms * 1e-3),
+            "eps_mean": float(((en.cpu().numpy().astype(np.int64) - inst.E_gs) / abs(inst.E_gs)).mean())}
+
+
 def tn(a, sg, wl, torch):
     """The tensor-network subsystem optimiser (exact l = 5 fragment
     marginals at beta = 2): eps_lin and time vs L, beta and l studies."""
@@ -300,6 +322,6 @@ def tuning(a, sg, wl, torch):
 
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "tn": tn, "tuning": tuning,
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "fragment_call": fragment_call, "tn": tn, "tuning": tuning,
           "wide": wide, "pticm": pticm}[name]
     return fn(a, sg, wl, torch)
