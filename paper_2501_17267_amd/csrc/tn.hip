@@ -579,6 +579,18 @@ int upload(sg_tn_plan &p)
                                 hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess)
             return fail(SG_EDEVICE, "sg_tn_decimate: LDS attribute (%d bytes)", need);
     }
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        if (side) (void)hipStreamDestroy(side);
+        if (fork) (void)hipEventDestroy(fork);
+        return fail(SG_EDEVICE, "sg_tn_decimate: side stream");
+    }
+    p.side = side;
+    p.fork = fork;
+    p.join = join;
     p.device = dev;
     return SG_OK;
 }
@@ -611,12 +623,21 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
     for (const TnPhase &P : p.phases) {
         const int n_items_q = P.n_lds + P.n_hbm;
         if (n_items_q == 0) continue;
+        // with both tiers present, the LDS tier runs on the side stream
+        // beside the workspace tier and joins before the decisions
+        const bool both = P.n_lds && P.n_hbm;
+        const hipStream_t lst = both ? static_cast<hipStream_t>(p.side) : st;
+        if (both && (hipEventRecord(static_cast<hipEvent_t>(p.fork), st) != hipSuccess ||
+                     hipStreamWaitEvent(lst, static_cast<hipEvent_t>(p.fork), 0) != hipSuccess))
+            return fail(SG_EDEVICE, "sg_tn_decimate: fork");
         if (P.n_lds) {
             int tb;
             const int bytes = lds_bytes(P, TROP, tb);
             hipLaunchKernelGGL(k_tn_lds<TROP>, dim3(static_cast<uint32_t>(n_inst) * P.n_lds * 2), dim3(kTnThreads),
-                               bytes, st, jb, wt, P.item0, n_items_q, P.n_lds, tb, P.lds_steps);
+                               bytes, lst, jb, wt, P.item0, n_items_q, P.n_lds, tb, P.lds_steps);
         }
+        if (both && hipEventRecord(static_cast<hipEvent_t>(p.join), lst) != hipSuccess)
+            return fail(SG_EDEVICE, "sg_tn_decimate: join");
         if (P.n_hbm) {
             const int64_t *epre = p.hbm_entry_pre.data() + P.hbm0;
             const int steps = P.hbm_steps;
@@ -689,6 +710,8 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                                    st, jb, bt);
             }
         }
+        if (both && hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.join), 0) != hipSuccess)
+            return fail(SG_EDEVICE, "sg_tn_decimate: join");
         const int64_t nd = static_cast<int64_t>(n_inst) * n_items_q;
         hipLaunchKernelGGL(k_tn_decide<TROP>, dim3(static_cast<uint32_t>((nd + 255) / 256)), dim3(256), 0, st, jb,
                            P.item0, n_items_q, n_inst);
@@ -733,8 +756,12 @@ int sg_tn_plan_destroy(sg_tn_plan *p)
 {
     if (!p) return fail(SG_EINVAL, "sg_tn_plan_destroy: NULL plan");
     clear_error();
+    if (p->side) (void)hipStreamSynchronize(static_cast<hipStream_t>(p->side));
     for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre})
         if (d) (void)hipFree(d);
+    if (p->side) (void)hipStreamDestroy(static_cast<hipStream_t>(p->side));
+    if (p->fork) (void)hipEventDestroy(static_cast<hipEvent_t>(p->fork));
+    if (p->join) (void)hipEventDestroy(static_cast<hipEvent_t>(p->join));
     delete p;
     return SG_OK;
 }

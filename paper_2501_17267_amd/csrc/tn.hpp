@@ -92,6 +92,9 @@ struct sg_tn_plan {
     int device = -1;
     void *d_shapes = nullptr, *d_steps = nullptr, *d_items = nullptr;
     void *d_entry_pre = nullptr;
+    // the LDS tier runs beside the workspace tier on a stream of the plan
+    // (default priority), forked from and joined to the caller's stream
+    void *side = nullptr, *fork = nullptr, *join = nullptr;   // hipStream_t, hipEvent_t x 2
 };
 
 namespace sg {
