@@ -127,8 +127,14 @@ def pt(a, sg, wl, torch):
     att = w.n_runs * w.n_steps * w.T * w.instance.L ** 3
     final_min = res["out"]["emin_trace"][:, -1].cpu().numpy().astype(np.int64)
     eps = (final_min - inst.E_gs) / abs(inst.E_gs)
+    rate = att / (ms * 1e-3)
+    ops = 20   # VALU lane-slots per attempt in the model of the SA bench line
+    peak = 256 * 4 * 16 * 2.4e9 / 1e12
     return {"metric": "spin-flip attempts/s (PT L=12, T=32, 128 runs x 2000 steps)",
-            "value": att / (ms * 1e-3), "unit": "spin-flip attempts/s", "ms_per_step": ms,
+            "value": rate, "unit": "spin-flip attempts/s", "ms_per_step": ms,
+            "roofline": {"bound": "alu", "achieved": ops * rate / 1e12, "peak": peak,
+                         "unit": "T 32-bit VALU ops/s", "frac": ops * rate / 1e12 / peak,
+                         "note": "one work group per run: 128 runs occupy 128 of the 256 CUs"},
             "exchange_attempts_per_step": w.n_runs * w.n_steps * (w.T - 1) / 2,
             "eps_best_mean": float(eps.mean()), "eps_best_min": float(eps.min())}
 
