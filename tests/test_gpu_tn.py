@@ -166,3 +166,27 @@ def test_argument_errors():
     small = torch.empty(1, dtype=torch.float64, device="cuda")
     with pytest.raises(sg.SgError):
         sg.tn_decimate(plan, J, beta=2.0, workspace=small)
+
+
+def test_l5_colour_classes_whole_free_fragments():
+    # colour classes at l = 5 (L = 6, period 3): the first class sees its whole
+    # fragment free (the largest tables of any plan); its sites score exactly 0
+    # and take +1; the tiers agree bit for bit; the ferromagnet decimates to
+    # its ground state
+    L, h = 6, 2
+    log("tn l=5 colour classes L=6")
+    plan, small = sg.TnPlan(L, h, 0), sg.TnPlan(L, h, 0, 8)
+    assert plan.info()["max_bits"] >= 20
+    Js, egs = _instances(L, 2, 606)
+    sp, en, sc = _run(plan, Js, 2.0, False)
+    sp8, en8, sc8 = _run(small, Js, 2.0, False)
+    np.testing.assert_array_equal(sp, sp8)
+    np.testing.assert_array_equal(sc, sc8)
+    ph = tn.phases(0, L, h)
+    for b in range(2):
+        assert np.all(sc[b][ph == 0] == 0) and np.all(sp[b][ph == 0] == 1)
+        assert en[b] == oracle.energy(Js[b], sp[b], (L, L, L)) and en[b] >= egs[b]
+        np.testing.assert_array_equal(sp[b], np.where(sc[b] >= 0, 1, -1))
+    J = np.full((6, L ** 3), -1, np.int8)
+    spf, enf, _ = _run(plan, [J], 2.0, True)
+    assert np.all(spf == 1) and enf[0] == -3 * L ** 3
