@@ -340,8 +340,9 @@ typedef struct sg_tn_args {
 } sg_tn_args;
 
 /* Decimate n_inst instances with the plan.  SG_EINVAL for bad arguments
- * (including a workspace below the minimum), SG_ENOMEM when the plan's
- * first upload fails.  Part of the work runs on a stream the plan owns,
+ * (including a workspace below the minimum), SG_ERANGE when 2 n_inst times
+ * the sites of a phase exceeds one launch (2^31 work groups), SG_ENOMEM
+ * when the plan's first upload fails.  Part of the work runs on a stream the plan owns,
  * forked from `stream` and joined back to it within the call's work, so
  * everything stays ordered with respect to `stream`; calls with one plan
  * must not overlap (they share that stream), and the plan must outlive them. */

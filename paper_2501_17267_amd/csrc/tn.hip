@@ -645,9 +645,14 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
             // batches: whole instances when one fits, else item ranges of one instance
             struct Range { int b0, nb, k0, k1; };
             std::vector<Range> batches;
+            // the most work groups a step launch of one instance can need
+            int64_t inst_blocks = 0;
+            for (int k = 0; k < P.n_hbm; ++k)
+                inst_blocks += 2 * tn_table_blocks(p.shapes[p.items[P.item0 + P.n_lds + k].shape].max_base);
+            const int max_per = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_inst, INT32_MAX / inst_blocks)));
             if (inst_bytes <= cap) {
-                int per = static_cast<int>(std::min<int64_t>(n_inst, 1));
-                while (per < n_inst &&
+                int per = 1;
+                while (per < max_per &&
                        batch_bytes(2 * P.n_hbm * int64_t{per + 1}, epre[P.n_hbm] * (per + 1), steps, P.n_hbm) <= cap)
                     ++per;
                 for (int b = 0; b < n_inst; b += per)
@@ -779,6 +784,9 @@ int sg_tn_decimate(sg_tn_plan *p, const sg_tn_args *a, void *stream)
                     static_cast<long long>(need));
     if (reinterpret_cast<uintptr_t>(a->workspace) % 256 != 0)
         return fail(SG_EINVAL, "sg_tn_decimate: workspace must be 256-byte aligned");
+    // one LDS-tier work group per (instance, site, value) of a phase
+    if (static_cast<int64_t>(a->n_inst) * p->max_items * 2 > INT32_MAX)
+        return fail(SG_ERANGE, "sg_tn_decimate: n_inst = %d exceeds one launch", a->n_inst);
     clear_error();
     int rc = upload(*p);
     if (rc != SG_OK) return rc;
