@@ -587,7 +587,12 @@ def tn_decimate(plan: TnPlan, J, beta: float = 2.0, tropical: bool = False, want
     en = torch.empty(n_inst, dtype=torch.int32, device=dev)
     sc = torch.empty((n_inst, N), dtype=torch.float64, device=dev) if want_score else None
     if workspace is None:
+        # the whole largest phase at once when that is at most 8 GiB, else
+        # 8 GiB (or the least that works): the workspace tables then go in passes
+        cap = 8 << 30
         nbytes = plan.workspace_bytes(n_inst, full=True)
+        if nbytes > cap:
+            nbytes = max(cap, plan.workspace_bytes(n_inst, full=False))
         workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
     args = sg_tn_args(J=J.data_ptr(), n_inst=n_inst, tropical=1 if tropical else 0, beta=float(beta),
                       spins_out=sp.data_ptr(), score_out=sc.data_ptr() if sc is not None else None,
