@@ -9,6 +9,8 @@ eps_lin(L)  20 instances per L, l = 5, beta = 2, wavefront order: mean and
 beta study  App. C: mean eps versus beta at one size.
 l study     App. B: mean eps versus the fragment edge at L = 20 (l = 3, 5;
             single-spin fragments are centred, so l is odd here).
+classes     mean eps of both forms at L = 12, l = 3 and 5, on every stand-in
+            tile class (0, 2, 4 or 6 frustrated faces, and mixed tiles).
 """
 from __future__ import annotations
 
@@ -98,4 +100,23 @@ def run(torch, sizes=(8, 12, 16, 20, 24, 32), n_inst=20, beta=2.0, beta_L=12,
         e = _eps(en, egs)
         out["l_study"]["rows"].append({"l": 2 * h + 1, "eps_mean": float(e.mean()), "eps_max": float(e.max())})
         log(f"tn l={2 * h + 1} L=20: eps_mean {e.mean():.5f}")
+    # both forms on every stand-in tile class
+    out["class_study"] = {"L": 12, "rows": []}
+    for h in (1, 2):
+        p = TnPlan(12, h, 1)
+        for cls in (-1, 0, 2, 4, 6):
+            Js, egs = [], []
+            for s_ in wl.tn_instances(12, n_inst):
+                J, _, e = make_instance(12, cls, s_.seed)
+                Js.append(np.asarray(J).reshape(6, 12 ** 3))
+                egs.append(e)
+            Jt = torch.from_numpy(np.stack(Js)).cuda()
+            egs = np.array(egs, np.int64)
+            row = {"l": 2 * h + 1, "class": cls}
+            for name, (b, trop) in (("beta2", (beta, False)), ("tropical", (1.0, True))):
+                _, en, _ = tn_decimate(p, Jt, b, trop, want_score=False)
+                e = _eps(en, egs)
+                row[name] = {"eps_mean": float(e.mean()), "eps_max": float(e.max()), "frac_exact": float(np.mean(e == 0))}
+            log(f"tn class {cls} l={2 * h + 1}: {row}")
+            out["class_study"]["rows"].append(row)
     return out
