@@ -225,6 +225,35 @@ def cpu_baseline_tn(sg, wl, L=20, n_sites=960):
             "kind": "oracle", "sample": f"{n_sites} random LDS-tier sites of one L={L} instance in {dt:.1f} s"}
 
 
+def cpu_baseline_pticm(sg, wl, steps=2000):
+    """The oracle's PT with cluster moves on the measured workload's instance
+    and ladder (L = 12, 2 x 4 walkers, beta 0.2 -> 2.0, moves on every slot),
+    one run of `steps` steps per host thread."""
+    import concurrent.futures as cf
+
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    T = 4
+    J, _, _ = oracle.make_instance(12, 6, wl.instance_seed("pt", 12))
+    beta = oracle.schedule(1, 0.2, 2.0, T)
+    thr = oracle.thresholds(beta, sg.SG_K_MAX)
+    # exchange tables up to their last nonzero entry
+    full = oracle.exchange_thresholds(beta, 4096)
+    M = int(max(np.nonzero(row)[0].max() + 1 if row.any() else 1 for row in full))
+    thrx = oracle.exchange_thresholds(beta, M)
+    seed = wl.philox_seed("pt")
+
+    def one(r):
+        oracle.pticm_run(12, J, seed, r, thr, thrx, steps, icm_from=0)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, range(cores)))
+    dt = time.perf_counter() - t0
+    att = cores * steps * 2 * T * 12 ** 3
+    return {"value": att / dt, "unit": "spin-flip attempts/s (with cluster moves)", "cores": cores,
+            "kind": "oracle", "sample": f"{cores} runs x {steps} steps, one per thread, {dt:.1f} s"}
+
+
 # ---------------------------------------------------------------------------
 
 def main():
@@ -255,6 +284,9 @@ def main():
         if a.workload == "fragment" and not a.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline_fragment(sg, wl)
+        if a.workload == "pticm" and not a.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_pticm(sg, wl)
         if a.workload == "tn" and not a.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline_tn(sg, wl)

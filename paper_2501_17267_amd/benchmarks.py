@@ -311,9 +311,15 @@ def pticm(a, sg, wl, torch):
     ms = _time(torch, fn, a.steps, a.warmup, stream)
     att = runs * steps * 2 * T * 12 ** 3
     fl = res["out"]["icm_flipped"].float().mean().item()
+    rate = att / (ms * 1e-3)
+    peak = 256 * 4 * 16 * 2.4e9 / 1e12
     return {"metric": "spin-flip attempts/s (PT+ICM L=12, 2 x 4 walkers, 128 runs x 200 steps)",
-            "value": att / (ms * 1e-3), "unit": "spin-flip attempts/s", "ms_per_call": ms,
-            "us_per_step": ms * 1e3 / steps, "sites_flipped_per_step_mean": fl}
+            "value": rate, "unit": "spin-flip attempts/s", "ms_per_call": ms,
+            "us_per_step": ms * 1e3 / steps, "sites_flipped_per_step_mean": fl,
+            "roofline": {"bound": "alu", "achieved": 20 * rate / 1e12, "peak": peak, "unit": "T 32-bit VALU ops/s",
+                         "frac": 20 * rate / 1e12 / peak,
+                         "note": "Metropolis work only (20 VALU slots per attempt); the cluster moves, one "
+                                 "growth pass per hop with a block barrier each, are the larger part of a step"}}
 
 
 def tuning(a, sg, wl, torch):
