@@ -225,7 +225,7 @@ def cpu_baseline_tn(sg, wl, L=20, n_sites=960):
             "kind": "oracle", "sample": f"{n_sites} random LDS-tier sites of one L={L} instance in {dt:.1f} s"}
 
 
-def cpu_baseline_pticm(sg, wl, steps=2000):
+def cpu_baseline_pticm(sg, wl, steps=5000):
     """The oracle's PT with cluster moves on the measured workload's instance
     and ladder (L = 12, 2 x 4 walkers, beta 0.2 -> 2.0, moves on every slot),
     one run of `steps` steps per host thread."""
