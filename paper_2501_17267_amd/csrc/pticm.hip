@@ -47,7 +47,7 @@ constexpr size_t pticm_lds_bytes(int T, int ng)
     const size_t W = 2 * static_cast<size_t>(T);
     return (W * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) + static_cast<size_t>(T) * kIcmThr + 3 * W +
             2 * (static_cast<size_t>(T) - 1) + 2 * static_cast<size_t>(ng) * G::SPIN_DW + 64 +
-            2 * static_cast<size_t>(T)) * 4;
+            2 * static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW)) * 4;
 }
 
 template <int L, bool JF>
@@ -72,6 +72,7 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     int32_t *s_misc = reinterpret_cast<int32_t *>(s_cl + job.G * SDW);   // 64 words: scan, flip counts
     int32_t *s_n = s_misc + 64;                              // [G] disagreeing sites per slot
     int32_t *s_tgt = s_n + T;                                // [G] seed position per slot
+    uint32_t *s_nz = reinterpret_cast<uint32_t *>(s_tgt + T);  // [6][SDW] nonzero-coupling masks
 
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = tid & 63, wave = tid >> 6;
@@ -95,6 +96,13 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
     if (tid < W) s_who[(tid / T) * T + s_pos[tid]] = tid;
+    // the bonds a cluster grows along (nonzero couplings), per dword and
+    // direction, for the whole run
+    for (int w = tid; w < SDW; w += NT) {
+        const int c = w / (G::NC * G::C), col = (w / G::C) % G::NC, m = w % G::C;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) s_nz[d * SDW + w] = Col::nonzero_coupling(s_j, c, col, d, m);
+    }
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
         constexpr int Q = G::N / 4;
@@ -209,17 +217,19 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
             while (grown) {
                 int add = 0;
                 for (int p = p0; p < p1; ++p) {
+                    // nothing left to add here: every disagreeing site is in
+                    const uint32_t open = s_q[p] & ~s_cl[p];
+                    if (!open) continue;
                     const int g = p / SDW, w = p - g * SDW;
                     const int c = w / (G::NC * G::C), col = (w / G::C) % G::NC, m = w % G::C;
                     uint32_t nb[6];
                     Col::nbr_dwords(s_cl + g * SDW, c, col, m, nb);
                     uint32_t reach = 0;
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) reach |= nb[d] & Col::nonzero_coupling(s_j, c, col, d, m);
-                    const uint32_t cur = s_cl[p];
-                    const uint32_t nw = reach & s_q[p] & ~cur;
+                    for (int d = 0; d < 6; ++d) reach |= nb[d] & s_nz[d * SDW + w];
+                    const uint32_t nw = reach & open;
                     if (nw) {
-                        s_cl[p] = cur | nw;
+                        s_cl[p] |= nw;
                         add = 1;
                     }
                 }
