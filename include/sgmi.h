@@ -8,10 +8,16 @@
  *   - minimise H(s) = sum over nearest-neighbour pairs J_ij s_i s_j over
  *     s in {-1,+1}^N (Sec. I, Eq. 1) on a periodic L x L x L lattice;
  *   - by fixed-sweep-count Metropolis simulated annealing and by parallel
- *     tempering (App. D);
+ *     tempering, with or without isoenergetic cluster moves (App. D);
  *   - scored by the optimality gap eps = (E - E_gs)/|E_gs| (Sec. I.A, Eq. 2)
  *     against the exactly known planted ground-state energy of a
- *     tile-planted instance (Sec. II).
+ *     tile-planted instance (Sec. II);
+ *   - batched over instances of mixed size, served with continuous batching,
+ *     and spread over many work-groups for few replicas of large lattices;
+ *   - inside the paper's linear-time meta-heuristic (Sec. I), whose
+ *     subsystem optimiser is either annealing on l^3 fragments or the exact
+ *     tensor-network fragment marginals of App. A-C (and their tropical,
+ *     zero-temperature form).
  *
  * Conventions shared by every call
  *   - Lattice: L even, 4 <= L <= SG_MAX_L, N = L^3, site i = x + L*(y + L*z),
@@ -37,7 +43,9 @@
  *     flips; k > 0 flips iff k <= K and u < thr[row][k-1].  Colour 0 sites
  *     are all updated before colour 1 sites in every sweep.
  *   - Device pointers are borrowed: the library keeps none of them after a
- *     call returns and allocates no device memory in these calls.  `stream`
+ *     call returns.  The sweep, exchange, energy and gap calls allocate no
+ *     device memory; plans, servers and the autotuner allocate theirs when
+ *     they are created and free it when they are destroyed.  `stream`
  *     is a hipStream_t passed as void* (NULL = the default stream).  Calls
  *     validate their arguments on the host, enqueue their kernels and return
  *     without waiting for the device.
