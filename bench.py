@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--workload", default="sa_batch", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "fragment_call", "tn", "tuning", "wide", "pticm", "microbench",
                              "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pt-groups", type=int, default=0,
+                    help="pt: work groups per run (0: as many as fill the device, 1: pt_run)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--variants", default=None,
@@ -254,6 +256,34 @@ def cpu_baseline_pticm(sg, wl, steps=5000):
             "kind": "oracle", "sample": f"{cores} runs x {steps} steps, one per thread, {dt:.1f} s"}
 
 
+def cpu_baseline_pt(sg, wl, steps=3000):
+    """The oracle's PT on the measured workload's instance and ladder (L = 12,
+    32 temperatures, beta 0.2 -> 3.0), one run of `steps` steps per host
+    thread."""
+    import concurrent.futures as cf
+
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    w = wl.pt()
+    L, T = w.instance.L, w.T
+    J, _, _ = oracle.make_instance(L, 6, w.instance.seed)
+    beta = oracle.schedule(1, w.beta0, w.beta1, T)
+    thr = oracle.thresholds(beta, sg.SG_K_MAX)
+    full = oracle.exchange_thresholds(beta, 4096)
+    M = int(max(np.nonzero(row)[0].max() + 1 if row.any() else 1 for row in full))
+    thrx = oracle.exchange_thresholds(beta, M)
+
+    def one(r):
+        oracle.pt_run(L, J, w.seed, r, thr, thrx, steps)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, range(cores)))
+    dt = time.perf_counter() - t0
+    att = cores * steps * T * L ** 3
+    return {"value": att / dt, "unit": "spin-flip attempts/s", "cores": cores,
+            "kind": "oracle", "sample": f"{cores} runs x {steps} steps, one per thread, {dt:.1f} s"}
+
+
 # ---------------------------------------------------------------------------
 
 def main():
@@ -284,6 +314,9 @@ def main():
         if a.workload == "fragment" and not a.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline_fragment(sg, wl)
+        if a.workload == "pt" and not a.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline_pt(sg, wl)
         if a.workload == "pticm" and not a.no_cpu_baseline:
             log("cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline_pticm(sg, wl)

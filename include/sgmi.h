@@ -174,6 +174,27 @@ int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
            const uint32_t *thrx, int8_t *spins, int32_t *energy, int32_t *pos,
            int32_t *emin_trace, uint32_t *swap_acc, void *stream);
 
+/* pt_run with each run spread over `groups` work groups (1, 2, 4 or 8; T a
+ * multiple of it; 0 picks the most that keep the launch within one work
+ * group per compute unit), for fewer runs than the device has compute
+ * units: group g sweeps walkers g*T/groups .. (g+1)*T/groups - 1, and the
+ * groups of a run pass their walkers' energies to each other through the
+ * workspace once per step, then make the same exchange decisions.  Results
+ * are identical to pt_run's, bit for bit.  waves: waves per work group (0,
+ * 4, 8, 12, 16; 0 picks).  workspace: device memory of
+ * sg_pt_split_workspace_bytes(n_runs, T) bytes, 8-byte aligned, owned by the
+ * caller; may be NULL only with groups = 1.  The call clears it on the
+ * stream first; its first int32 is 0 after the call completes, 1 if a group
+ * gave up waiting on another (a group waits at most a few seconds; the
+ * results are then invalid).  Calls sharing one workspace must not overlap.
+ * SG_EUNSUPPORTED when the launch's work groups would not all be resident on
+ * the device at once. */
+int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, int32_t groups, int32_t waves,
+                    const uint32_t *thr, const uint32_t *thrx, int8_t *spins, int32_t *energy,
+                    int32_t *pos, int32_t *emin_trace, uint32_t *swap_acc, void *workspace,
+                    int64_t workspace_bytes, void *stream);
+size_t sg_pt_split_workspace_bytes(int32_t n_runs, int32_t T);
+
 /* ---- parallel tempering with isoenergetic cluster moves (App. D, PT+ICM) ----
  * The paper only names the cluster moves; this is Houdayer's two-replica
  * move as combined with PT by Zhu, Ochoa and Katzgraber (2015).  Two copies

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libsgmi.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "sgmi.h")
 
 SG_OK = 0
+SG_EINVAL = -1
 SG_MAX_L = 64
 SG_K_MAX = 24
 SG_LDS_MAX_L = 24
@@ -143,6 +144,10 @@ def lib() -> ctypes.CDLL:
     L.sg_check_instance.argtypes = [c.POINTER(sg_instance), vp, vp]
     L.sa_anneal.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_sa_args), vp, vp, vp, vp, vp]
     L.pt_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), vp, vp, vp, vp, vp, vp, vp, vp]
+    L.sg_pt_run_split.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), c.c_int32, c.c_int32, vp, vp, vp,
+                                  vp, vp, vp, vp, vp, c.c_int64, vp]
+    L.sg_pt_split_workspace_bytes.restype = c.c_size_t
+    L.sg_pt_split_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
     L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
     L.sg_pticm_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pticm_args), vp, vp, vp, vp, vp, vp, vp,
                                vp, vp]
@@ -172,7 +177,7 @@ def lib() -> ctypes.CDLL:
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
                "sg_fragment_decimate", "sg_pticm_run", "sg_tn_plan_create", "sg_tn_plan_info_get",
                "sg_tn_plan_destroy", "sg_tn_plan_program", "sg_tn_decimate",
-               "pt_run", "energy", "epsilon"):
+               "pt_run", "sg_pt_run_split", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
     return L
@@ -351,10 +356,15 @@ def sa_anneal(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0:
 
 def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0: int = 0,
            step0: int = 0, spins=None, pos=None, want_trace: bool = False,
-           want_swaps: bool = False, stream=None):
+           want_swaps: bool = False, stream=None, groups: int = 1, waves: int = 0, workspace=None):
     """Parallel tempering.  thr: device [T][K]; thrx: device [T-1][M].
+    groups != 1 (or waves != 0) calls sg_pt_run_split: each run spread over
+    that many work groups (0: as many as fill the device), same results;
+    workspace: a device tensor of at least pt_split_workspace_bytes(n_runs,
+    T) bytes, allocated here when None.
     Returns dict(spins [n_runs][T][N], energy [n_runs][T], pos [n_runs][T],
-    emin_trace, swap_acc)."""
+    emin_trace, swap_acc, and for the split form `workspace`, whose first
+    int32 is 1 if a work group gave up waiting on another)."""
     import torch
     dev = inst.J.device
     N = inst.L ** 3
@@ -368,11 +378,30 @@ def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0
     sw = torch.zeros((n_runs, T - 1), dtype=torch.int32, device=dev) if want_swaps else None
     args = sg_pt_args(n_runs=n_runs, run0=run0, T=T, n_steps=n_steps, step0=step0, K=K, M=M,
                       init_random=1 if init_random else 0, seed=seed & 0xFFFFFFFFFFFFFFFF)
-    _check(lib().pt_run(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
-                        _dptr(thrx, "thrx"), _dptr(sp, "spins"), _dptr(en, "energy"),
-                        _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
-                        _stream(stream)), "pt_run")
-    return {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+    out = {"spins": sp, "energy": en, "pos": ps, "emin_trace": tr, "swap_acc": sw}
+    if groups == 1 and waves == 0:
+        _check(lib().pt_run(ctypes.byref(inst.struct()), ctypes.byref(args), _dptr(thr, "thr"),
+                            _dptr(thrx, "thrx"), _dptr(sp, "spins"), _dptr(en, "energy"),
+                            _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
+                            _stream(stream)), "pt_run")
+        return out
+    nbytes = pt_split_workspace_bytes(n_runs, T)
+    if workspace is None:
+        workspace = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=dev)
+    _check(lib().sg_pt_run_split(ctypes.byref(inst.struct()), ctypes.byref(args), groups, waves,
+                                 _dptr(thr, "thr"), _dptr(thrx, "thrx"), _dptr(sp, "spins"), _dptr(en, "energy"),
+                                 _dptr(ps, "pos"), _dptr(tr, "emin_trace"), _dptr(sw, "swap_acc"),
+                                 _dptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                                 _stream(stream)), "sg_pt_run_split")
+    out["workspace"] = workspace
+    return out
+
+
+def pt_split_workspace_bytes(n_runs: int, T: int) -> int:
+    n = lib().sg_pt_split_workspace_bytes(n_runs, T)
+    if n == 0:
+        raise SgError(SG_EINVAL, f"sg_pt_split_workspace_bytes: n_runs = {n_runs}, T = {T}")
+    return int(n)
 
 
 def pticm_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, icm_from: int = 0,

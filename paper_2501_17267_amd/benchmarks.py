@@ -121,9 +121,17 @@ def pt(a, sg, wl, torch):
     stream = torch.cuda.current_stream()
     res = {}
 
+    groups = getattr(a, "pt_groups", 0)
+    ws = None
+    if groups != 1:
+        ws = torch.empty((sg.pt_split_workspace_bytes(w.n_runs, w.T) + 7) // 8, dtype=torch.int64, device="cuda")
+
     def fn():
-        res["out"] = sg.pt_run(inst, thr, thrx, w.n_runs, w.n_steps, w.seed, want_trace=True)
+        res["out"] = sg.pt_run(inst, thr, thrx, w.n_runs, w.n_steps, w.seed, want_trace=True, groups=groups,
+                               workspace=ws)
     ms = _time(torch, fn, a.steps, a.warmup, stream)
+    if ws is not None and int(ws.view(torch.int32)[0].item()) != 0:
+        raise RuntimeError("pt: a work group gave up waiting on another (status word set)")
     att = w.n_runs * w.n_steps * w.T * w.instance.L ** 3
     final_min = res["out"]["emin_trace"][:, -1].cpu().numpy().astype(np.int64)
     eps = (final_min - inst.E_gs) / abs(inst.E_gs)
@@ -134,7 +142,10 @@ def pt(a, sg, wl, torch):
             "value": rate, "unit": "spin-flip attempts/s", "ms_per_step": ms,
             "roofline": {"bound": "alu", "achieved": ops * rate / 1e12, "peak": peak,
                          "unit": "T 32-bit VALU ops/s", "frac": ops * rate / 1e12 / peak,
-                         "note": "one work group per run: 128 runs occupy 128 of the 256 CUs"},
+                         "note": ("one work group per run: 128 runs occupy 128 of the 256 CUs" if groups == 1 else
+                                  "each run spread over work groups (sg_pt_run_split) so that the launch "
+                                  "fills the 256 CUs")},
+            "pt_groups": "auto" if groups == 0 else groups,
             "exchange_attempts_per_step": w.n_runs * w.n_steps * (w.T - 1) / 2,
             "eps_best_mean": float(eps.mean()), "eps_best_min": float(eps.min())}
 

@@ -1,10 +1,30 @@
-// pt.hip -- parallel tempering kernel (App. D) and its C-ABI entry point.
+// pt.hpp -- the parallel tempering kernel (App. D), shared by the
+// one-group-per-run entry point (pt.hip) and the split form (pt_split.hip).
 //
-// One work group runs one PT run: the T walkers of the run, the encoded
-// couplings and the T rows of thresholds are LDS-resident.  A step is a
-// colour-0 pass over all walkers' columns, a colour-1 pass, then the
-// even/odd replica exchange done by one lane per ladder pair, all inside
-// the group, so a run never leaves its compute unit.
+// One work group holds the walkers it sweeps, the encoded couplings and the
+// T rows of thresholds in LDS.  A step is a colour-0 pass over its walkers'
+// columns, a colour-1 pass, then the even/odd replica exchange done by one
+// lane per ladder pair.
+//
+// Without SPLIT a work group runs a whole PT run, so a run never leaves its
+// compute unit.  With SPLIT a run's T walkers are dealt to G work groups
+// (T/G each, walker w in group w / (T/G)); after each step's sweep every
+// group publishes its walkers' energies as 64-bit words (step tag in the
+// high half, energy in the low half) in a device-memory mailbox and reads
+// the other groups' words of the same step.  Every group then holds all T
+// energies and makes the same exchange decisions from the same Philox
+// counters, so the ladder stays identical in every group and the results
+// are those of the one-group kernel, bit for bit.
+//
+// Mailbox safety: step ti writes half (ti mod 2) of the run's mailbox with
+// tag ti + 1.  A group overwrites that half again only at step ti + 2,
+// after its exchange of step ti + 1, which needs every other group's tag
+// ti + 2 word, which each group writes only after reading the tag ti + 1
+// words.  So no word is overwritten before every group has read it, and a
+// reader never sees a later tag than the one it waits for.  The mailbox is
+// zeroed by a fill kernel queued before the PT kernel (tags start at 1).
+#pragma once
+
 #include <algorithm>
 
 #include "common.hpp"
@@ -30,23 +50,32 @@ struct PtJob {
     int32_t M;
     int32_t init_random;
     int32_t mx;             // exchange-table entries per ladder pair copied to LDS
+    int32_t n_runs;
+    int32_t G;              // work groups per run (SPLIT)
+    uint64_t *mbox;         // [n_runs][2][T] tagged energies (SPLIT)
+    int32_t *status;        // set to 1 when a wait on another group gives up (SPLIT)
 };
 
 constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
+
+// A wait for another group's energies polls at most this many times (each
+// poll is a device-scope load of about a microsecond, then a short sleep);
+// past that the run is abandoned: status is set, later waits are skipped
+// and the kernel still runs to its end.
+constexpr int kPtPollLimit = 1 << 22;
 
 template <int L>
 struct PtCfg {
     static constexpr bool JF = (L <= 12);
 };
 
-// Waves per work group for T walkers of size L: the T * L^2/2 column units
-// of a colour phase are dealt to NW * 64 lanes in ceil(units / (NW*64))
-// passes.  Pick the NW with the least idle lane-passes (passes * NW), the
-// larger NW on ties (more waves to hide LDS latency).
+// Waves per work group for `units` column units of a colour phase dealt to
+// NW * 64 lanes in ceil(units / (NW*64)) passes.  Pick the NW with the
+// least idle lane-passes (passes * NW), the larger NW on ties (more waves
+// to hide LDS latency).
 constexpr int kPtWaves[] = {4, 8, 12, 16};
-inline int pt_waves(int L, int T)
+inline int pt_waves_for_units(int units)
 {
-    const int units = T * L * L / 2;
     int best = 4, best_cost = 1 << 30;
     for (int nw : kPtWaves) {
         const int passes = (units + nw * 64 - 1) / (nw * 64);
@@ -59,13 +88,31 @@ inline int pt_waves(int L, int T)
     return best;
 }
 
-// LDS of one run: T spin blocks, the couplings, T threshold tables, four
-// per-walker words and the first mx entries of each pair's exchange table
+inline int pt_waves(int L, int T) { return pt_waves_for_units(T * L * L / 2); }
+
+// Waves per work group of the split form, whose groups mostly have a compute
+// unit each: the fewest passes, then the fewest waves that reach them.
+inline int pt_split_waves(int units)
+{
+    int best = 4, best_passes = 1 << 30;
+    for (int nw : kPtWaves) {
+        const int passes = (units + nw * 64 - 1) / (nw * 64);
+        if (passes < best_passes) {
+            best = nw;
+            best_passes = passes;
+        }
+    }
+    return best;
+}
+
+// LDS of one work group: its spin blocks (TG walkers), the couplings, T
+// threshold tables, four per-walker words and the first mx entries of each
+// pair's exchange table
 template <int L, bool JF>
-constexpr size_t pt_lds_bytes(int T, int mx)
+constexpr size_t pt_lds_bytes(int TG, int T, int mx)
 {
     using G = Geo<L>;
-    return (static_cast<size_t>(T) * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) +
+    return (static_cast<size_t>(TG) * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) +
             static_cast<size_t>(T) * kPtThr + 4 * static_cast<size_t>(T) +
             static_cast<size_t>(T - 1) * static_cast<size_t>(mx)) * 4;
 }
@@ -82,17 +129,41 @@ constexpr int pt_umax()
     return (regs / per) < 4 ? regs / per : 4;
 }
 
-template <int L, int NW, bool JF, bool PREP>
-__global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t k1)
+// UMAX: prepared units per lane (0: units are formed at every sweep);
+// WPE: least waves per SIMD the register allocation must allow (0: any).
+template <int L, int NW, bool JF, int UMAX, bool SPLIT, int WPE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, NW * 64), amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_pt(PtJob job, uint32_t k0, uint32_t k1)
 {
+    constexpr bool PREP = UMAX > 0;
     using G = Geo<L>;
     using Col = Column<L, JF>;
     constexpr int NT = NW * 64;
     constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
     extern __shared__ uint32_t lds[];
     const int T = job.T;
+    const int tid = static_cast<int>(threadIdx.x);
+
+    // run and group of this work group.  SPLIT: blocks are dealt round
+    // robin to the eight XCDs, so blocks b and b + 8 share an XCD (and its
+    // L2); the G groups of a run take blocks 8 apart.
+    int run, g, TG;
+    if constexpr (SPLIT) {
+        const int b = static_cast<int>(blockIdx.x);
+        const int j = b >> 3;
+        TG = T / job.G;
+        g = j % job.G;
+        run = (j / job.G) * 8 + (b & 7);
+        if (run >= job.n_runs) return;   // whole group, before any barrier
+    } else {
+        TG = T;
+        g = 0;
+        run = static_cast<int>(blockIdx.x);
+    }
+    const int w0 = g * TG;   // first walker of the group
+
     uint32_t *s_spin = lds;
-    uint32_t *s_j = s_spin + T * G::SPIN_DW;
+    uint32_t *s_j = s_spin + TG * G::SPIN_DW;
     uint32_t *s_thr = s_j + JDW;
     int32_t *s_E = reinterpret_cast<int32_t *>(s_thr + T * kPtThr);
     int32_t *s_pos = s_E + T;
@@ -101,13 +172,11 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     uint32_t *s_thrx = reinterpret_cast<uint32_t *>(s_sw + T);
     const int mx = job.mx;
 
-    const int tid = static_cast<int>(threadIdx.x);
-    const int run = static_cast<int>(blockIdx.x);
     const uint32_t chain = job.run0 + static_cast<uint32_t>(run);
     int8_t *spins = job.spins + static_cast<int64_t>(run) * T * G::N;
 
     // ---- set-up ---------------------------------------------------------
-    for (int w = tid; w < T * G::SPIN_DW; w += NT) s_spin[w] = 0u;
+    for (int w = tid; w < TG * G::SPIN_DW; w += NT) s_spin[w] = 0u;
     for (int w = tid; w < T * kPtThr; w += NT) {
         const int slot = w / kPtThr, e = w - slot * kPtThr;
         s_thr[w] = thr_entry(job.thr + slot * job.K, job.K, e);
@@ -129,39 +198,40 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
         constexpr int Q = G::N / 4;
-        for (int w = tid; w < T * Q; w += NT) {
+        for (int w = tid; w < TG * Q; w += NT) {
             const int wk = w / Q;
             const int q = w - wk * Q;
             load_spins_one<L>(sb + wk * G::SPIN_DW * 4, q, job.init_random != 0,
-                              spins + static_cast<int64_t>(wk) * G::N, static_cast<uint32_t>(wk), chain,
+                              spins + static_cast<int64_t>(w0 + wk) * G::N, static_cast<uint32_t>(w0 + wk), chain,
                               k0, k1);
         }
     }
     __syncthreads();
-    for (int u = tid; u < T * G::NC; u += NT) {
+    for (int u = tid; u < TG * G::NC; u += NT) {
         const int wk = u / G::NC;
         const int col = u - wk * G::NC;
-        atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * G::SPIN_DW, s_j, col));
+        atomicAdd(&s_E[w0 + wk], Col::column_energy_of(s_spin + wk * G::SPIN_DW, s_j, col));
     }
     __syncthreads();
 
     // prepared units: a lane keeps the same (walker, column) units for the
     // whole run (the launcher guarantees they number at most UMAX)
-    constexpr int UMAX = PREP ? pt_umax<L, NW>() : 1;
-    typename Col::Unit un[UMAX];
-    int wks[UMAX];
-    bool act[UMAX];
+    constexpr int US = PREP ? UMAX : 1;
+    typename Col::Unit un[US];
+    int wks[US];
+    bool act[US];
     if constexpr (PREP) {
 #pragma unroll
         for (int i = 0; i < UMAX; ++i) {
             const int u = tid + i * NT;
-            act[i] = u < T * G::NC;
+            act[i] = u < TG * G::NC;
             const int ua = act[i] ? u : 0;
             const int wk = ua / G::NC;
             wks[i] = wk;
-            un[i] = Col::make_unit(ua - wk * G::NC, static_cast<uint32_t>(wk), chain, k0, k1);
+            un[i] = Col::make_unit(ua - wk * G::NC, static_cast<uint32_t>(w0 + wk), chain, k0, k1);
         }
     }
+    bool dead = false;   // SPLIT: a wait gave up (wave 0 only)
 
     // ---- steps ------------------------------------------------------------
     for (int ti = 0; ti < job.n_steps; ++ti) {
@@ -172,9 +242,9 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
 #pragma unroll
                 for (int i = 0; i < UMAX; ++i) {
                     if (!act[i]) continue;
-                    const int wk = wks[i];
+                    const int wk = w0 + wks[i];
                     const int32_t dE = Col::template metropolis_unit<true>(
-                        s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, un[i],
+                        s_spin + wks[i] * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, un[i],
                         2u * t + static_cast<uint32_t>(c), k0, k1);
                     if (dE != 0) atomicAdd(&s_E[wk], dE);
                 }
@@ -182,15 +252,49 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
             }
         } else {
             for (int c = 0; c < 2; ++c) {
-                for (int u = tid; u < T * G::NC; u += NT) {
-                    const int wk = u / G::NC;
-                    const int col = u - wk * G::NC;
+                for (int u = tid; u < TG * G::NC; u += NT) {
+                    const int wl = u / G::NC;
+                    const int col = u - wl * G::NC;
+                    const int wk = w0 + wl;
                     const int32_t dE = Col::template metropolis<true>(
-                        s_spin + wk * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, col,
+                        s_spin + wl * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, col,
                         2u * t + static_cast<uint32_t>(c), static_cast<uint32_t>(wk), chain, k0, k1);
                     if (dE != 0) atomicAdd(&s_E[wk], dE);
                 }
                 __syncthreads();
+            }
+        }
+        if constexpr (SPLIT) {
+            // wave 0: publish this group's energies, collect the others',
+            // then exchange; T <= 64 walkers, one lane each
+            if (tid < 64) {
+                const int w = tid;
+                uint64_t *box = job.mbox + (static_cast<int64_t>(run) * 2 + (ti & 1)) * T;
+                const uint32_t tag = static_cast<uint32_t>(ti) + 1u;
+                const bool mine = w >= w0 && w < w0 + TG;
+                if (mine)
+                    __hip_atomic_store(box + w, (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(s_E[w]),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool gave_up = false;
+                if (w < T && !mine && !dead) {
+                    uint64_t v = 0;
+                    for (int n = 0;; ++n) {
+                        v = __hip_atomic_load(box + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (static_cast<uint32_t>(v >> 32) == tag) break;
+                        if (n + 1 == kPtPollLimit) {
+                            gave_up = true;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    s_E[w] = static_cast<int32_t>(static_cast<uint32_t>(v));
+                }
+                if (__any(gave_up)) {
+                    if (!dead && w == 0) job.status[0] = 1;
+                    dead = true;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
         }
         // exchange of ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ...
@@ -215,8 +319,11 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
                 s_sw[k] += 1;
             }
         }
-        if (job.emin_trace && tid >= 64 && tid < 128) {
-            const int lane = tid - 64;
+        // minimum energy of the step: another wave when the energies are
+        // all local, wave 0 (which collected them) in the split form
+        constexpr int kTraceLo = SPLIT ? 0 : 64;
+        if (job.emin_trace && g == 0 && tid >= kTraceLo && tid < kTraceLo + 64) {
+            const int lane = tid - kTraceLo;
             int32_t e = 0x7FFFFFFF;
             for (int w = lane; w < T; w += 64) e = min(e, s_E[w]);
             for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
@@ -229,77 +336,110 @@ __global__ __launch_bounds__(NW * 64) void k_pt(PtJob job, uint32_t k0, uint32_t
     {
         const uint8_t *sb = reinterpret_cast<const uint8_t *>(s_spin);
         constexpr int Q = G::N / 4;
-        for (int w = tid; w < T * Q; w += NT) {
+        for (int w = tid; w < TG * Q; w += NT) {
             const int wk = w / Q;
             const int q = w - wk * Q;
-            store_spins_one<L>(sb + wk * G::SPIN_DW * 4, q, spins + static_cast<int64_t>(wk) * G::N);
+            store_spins_one<L>(sb + wk * G::SPIN_DW * 4, q, spins + static_cast<int64_t>(w0 + wk) * G::N);
         }
     }
-    if (tid < T) {
+    // group 0 holds every walker's final energy (the last step's mailbox)
+    if (g == 0 && tid < T) {
         job.energy[run * T + tid] = s_E[tid];
         job.pos[run * T + tid] = s_pos[tid];
         if (job.swap_acc && tid + 1 < T) job.swap_acc[run * (T - 1) + tid] += static_cast<uint32_t>(s_sw[tid]);
     }
 }
 
-template <int L, int NW>
-static int launch_pt_nw(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+// Launch T-walker runs with G work groups each (G = 1 without SPLIT) and NW
+// waves per group; `lds_cap` bounds one group's LDS (a fraction of the
+// CU's 160 KB lets several groups share a CU).  SPLIT launches
+// ceil(n_runs/8) * 8 * G groups.
+template <int L, int NW, int UMAX, bool SPLIT, int WPE>
+static int launch_pt_cfg(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream, const char *who,
+                         size_t lds_cap = 160 * 1024)
 {
     using Cfg = PtCfg<L>;
-    constexpr size_t kLds = 160 * 1024;
-    const size_t base = pt_lds_bytes<L, Cfg::JF>(job.T, 0);
-    if (base > kLds)
-        return fail(SG_EUNSUPPORTED, "pt_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, base);
+    const int TG = job.T / job.G;
+    const size_t base = pt_lds_bytes<L, Cfg::JF>(TG, job.T, 0);
+    if (base > lds_cap)
+        return fail(SG_EUNSUPPORTED, "%s: L = %d with %d walkers per group needs %zu bytes of LDS", who, L, TG, base);
     // the exchange-table prefix held in LDS: up to 128 entries per pair,
     // as many as the LDS left over allows (later entries are read from HBM)
     job.mx = static_cast<int32_t>(std::min<size_t>({static_cast<size_t>(job.M), 128,
-                                                   (kLds - base) / (4 * static_cast<size_t>(job.T - 1))}));
-    const size_t bytes = pt_lds_bytes<L, Cfg::JF>(job.T, job.mx);
-    const int units = job.T * Geo<L>::NC;
-    const int upl = (units + NW * 64 - 1) / (NW * 64);
-    auto kern = (upl <= pt_umax<L, NW>()) ? k_pt<L, NW, Cfg::JF, true> : k_pt<L, NW, Cfg::JF, false>;
+                                                   (lds_cap - base) / (4 * static_cast<size_t>(job.T - 1))}));
+    const size_t bytes = pt_lds_bytes<L, Cfg::JF>(TG, job.T, job.mx);
+    const int units = TG * Geo<L>::NC;
+    if (UMAX > 0 && (units + NW * 64 - 1) / (NW * 64) > UMAX)
+        return fail(SG_EUNSUPPORTED, "%s: %d units per colour exceed %d lanes x %d prepared units", who, units,
+                    NW * 64, UMAX);
+    auto kern = k_pt<L, NW, Cfg::JF, UMAX, SPLIT, WPE>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
-    if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: LDS attribute: %s", hipGetErrorString(err));
+    if (err != hipSuccess) return fail(SG_EDEVICE, "%s: LDS attribute: %s", who, hipGetErrorString(err));
+    const int blocks = SPLIT ? ((n_runs + 7) / 8) * 8 * job.G : n_runs;
+    if constexpr (SPLIT) {
+        // every group of the launch must be resident at once: a group waits
+        // on the other groups of its run
+        int dev = 0, n_cu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), NW * 64,
+                                                         bytes) != hipSuccess)
+            return fail(SG_EDEVICE, "%s: occupancy query failed", who);
+        if (static_cast<int64_t>(blocks) > static_cast<int64_t>(per_cu) * n_cu)
+            return fail(SG_EUNSUPPORTED, "%s: %d work groups exceed the %d x %d the device holds at once", who, blocks,
+                        per_cu, n_cu);
+    }
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(NW * 64), bytes, stream, job, k0, k1);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NW * 64), bytes, stream, job, k0, k1);
     err = hipGetLastError();
-    if (err != hipSuccess) return fail(SG_EDEVICE, "pt_run: launch failed: %s", hipGetErrorString(err));
+    if (err != hipSuccess) return fail(SG_EDEVICE, "%s: launch failed: %s", who, hipGetErrorString(err));
     return SG_OK;
 }
 
-template <int L>
-static int launch_pt(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
+// one-group-per-run launch (and the split form's default): prepared units
+// when they fit the register budget of NW waves
+template <int L, int NW, bool SPLIT>
+static int launch_pt_nw(const PtJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream, const char *who)
 {
-    switch (pt_waves(L, job.T)) {
-    case 4: return launch_pt_nw<L, 4>(job, n_runs, k0, k1, stream);
-    case 8: return launch_pt_nw<L, 8>(job, n_runs, k0, k1, stream);
-    case 12: return launch_pt_nw<L, 12>(job, n_runs, k0, k1, stream);
-    default: return launch_pt_nw<L, 16>(job, n_runs, k0, k1, stream);
+    constexpr int UM = pt_umax<L, NW>();
+    const int units = job.T / job.G * Geo<L>::NC;
+    const int upl = (units + NW * 64 - 1) / (NW * 64);
+    if (UM > 0 && upl <= UM) return launch_pt_cfg<L, NW, UM, SPLIT, 0>(job, n_runs, k0, k1, stream, who);
+    return launch_pt_cfg<L, NW, 0, SPLIT, 0>(job, n_runs, k0, k1, stream, who);
+}
+
+template <int L, bool SPLIT>
+static int launch_pt(const PtJob &job, int n_runs, int nw, uint32_t k0, uint32_t k1, hipStream_t stream,
+                     const char *who)
+{
+    switch (nw) {
+    case 4: return launch_pt_nw<L, 4, SPLIT>(job, n_runs, k0, k1, stream, who);
+    case 8: return launch_pt_nw<L, 8, SPLIT>(job, n_runs, k0, k1, stream, who);
+    case 12: return launch_pt_nw<L, 12, SPLIT>(job, n_runs, k0, k1, stream, who);
+    default: return launch_pt_nw<L, 16, SPLIT>(job, n_runs, k0, k1, stream, who);
     }
 }
 
-}  // namespace sg
-
-using namespace sg;
-
-extern "C" int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
-                      const uint32_t *thrx, int8_t *spins, int32_t *energy_out, int32_t *pos,
-                      int32_t *emin_trace, uint32_t *swap_acc, void *stream)
+// Host validation shared by both entry points; fills job from the arguments.
+inline int pt_prepare(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr, const uint32_t *thrx,
+                      int8_t *spins, int32_t *energy_out, int32_t *pos, int32_t *emin_trace, uint32_t *swap_acc,
+                      const char *who, PtJob &job)
 {
-    if (!inst || !args) return fail(SG_EINVAL, "pt_run: NULL instance or args");
-    if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "pt_run: L = %d must be even in [4, %d]", inst->L, SG_MAX_L);
-    if (!inst->J && !inst->jenc) return fail(SG_EINVAL, "pt_run: instance has no couplings");
-    if (!thr || !thrx || !spins || !energy_out || !pos) return fail(SG_EINVAL, "pt_run: NULL array");
-    if (args->n_runs < 1 || args->n_steps < 1) return fail(SG_EINVAL, "pt_run: n_runs = %d, n_steps = %d", args->n_runs, args->n_steps);
-    if (args->T < 2 || args->T > SG_PT_MAX_T) return fail(SG_EINVAL, "pt_run: T = %d outside [2, %d]", args->T, SG_PT_MAX_T);
-    if (args->K < 1 || args->K > SG_K_MAX || args->M < 1) return fail(SG_EINVAL, "pt_run: K = %d, M = %d", args->K, args->M);
+    if (!inst || !args) return fail(SG_EINVAL, "%s: NULL instance or args", who);
+    if (!lattice_ok(inst->L)) return fail(SG_EINVAL, "%s: L = %d must be even in [4, %d]", who, inst->L, SG_MAX_L);
+    if (!inst->J && !inst->jenc) return fail(SG_EINVAL, "%s: instance has no couplings", who);
+    if (!thr || !thrx || !spins || !energy_out || !pos) return fail(SG_EINVAL, "%s: NULL array", who);
+    if (args->n_runs < 1 || args->n_steps < 1)
+        return fail(SG_EINVAL, "%s: n_runs = %d, n_steps = %d", who, args->n_runs, args->n_steps);
+    if (args->T < 2 || args->T > SG_PT_MAX_T) return fail(SG_EINVAL, "%s: T = %d outside [2, %d]", who, args->T, SG_PT_MAX_T);
+    if (args->K < 1 || args->K > SG_K_MAX || args->M < 1) return fail(SG_EINVAL, "%s: K = %d, M = %d", who, args->K, args->M);
     if (args->step0 < 0 || static_cast<int64_t>(args->step0) + args->n_steps > (1 << 30))
-        return fail(SG_ERANGE, "pt_run: steps must stay below 2^30");
+        return fail(SG_ERANGE, "%s: steps must stay below 2^30", who);
     if (static_cast<uint64_t>(args->run0) + static_cast<uint64_t>(args->n_runs) > 0xFFFFFFFFull)
-        return fail(SG_ERANGE, "pt_run: run counter words overflow");
-    if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0) return fail(SG_EINVAL, "pt_run: spins must be 4-byte aligned");
-    PtJob job{};
+        return fail(SG_ERANGE, "%s: run counter words overflow", who);
+    if ((reinterpret_cast<uintptr_t>(spins) & 3u) != 0) return fail(SG_EINVAL, "%s: spins must be 4-byte aligned", who);
+    job = PtJob{};
     job.J = inst->J;
     job.jenc = inst->jenc;
     job.thr = thr;
@@ -316,17 +456,25 @@ extern "C" int pt_run(const sg_instance *inst, const sg_pt_args *args, const uin
     job.K = args->K;
     job.M = args->M;
     job.init_random = args->init_random ? 1 : 0;
-    clear_error();
-    const uint32_t k0 = static_cast<uint32_t>(args->seed), k1 = static_cast<uint32_t>(args->seed >> 32);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    switch (inst->L) {
-    case 4: return launch_pt<4>(job, args->n_runs, k0, k1, st);
-    case 6: return launch_pt<6>(job, args->n_runs, k0, k1, st);
-    case 8: return launch_pt<8>(job, args->n_runs, k0, k1, st);
-    case 10: return launch_pt<10>(job, args->n_runs, k0, k1, st);
-    case 12: return launch_pt<12>(job, args->n_runs, k0, k1, st);
-    case 14: return launch_pt<14>(job, args->n_runs, k0, k1, st);
-    case 16: return launch_pt<16>(job, args->n_runs, k0, k1, st);
-    default: return fail(SG_EUNSUPPORTED, "pt_run: L = %d is above the LDS-resident PT range", inst->L);
+    job.n_runs = args->n_runs;
+    job.G = 1;
+    return SG_OK;
+}
+
+template <bool SPLIT>
+inline int pt_dispatch(int L, const PtJob &job, int n_runs, int nw, uint32_t k0, uint32_t k1, hipStream_t st,
+                       const char *who)
+{
+    switch (L) {
+    case 4: return launch_pt<4, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 6: return launch_pt<6, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 8: return launch_pt<8, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 10: return launch_pt<10, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 12: return launch_pt<12, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 14: return launch_pt<14, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    case 16: return launch_pt<16, SPLIT>(job, n_runs, nw, k0, k1, st, who);
+    default: return fail(SG_EUNSUPPORTED, "%s: L = %d is above the LDS-resident PT range", who, L);
     }
 }
+
+}  // namespace sg

@@ -1,0 +1,82 @@
+// pt_split.hip -- sg_pt_run_split: parallel tempering (App. D) with each
+// run spread over G work groups (the kernel and its mailbox protocol are in
+// pt.hpp).  For fewer runs than compute units: the one-group form leaves
+// the rest of the device idle.
+#include "pt.hpp"
+
+namespace sg {
+
+constexpr size_t kPtSplitHeader = 256;   // status word, padded
+
+// zeroes the mailbox (tags start at 1) and the status word
+__global__ __launch_bounds__(256) void k_pt_split_clear(uint64_t *mbox, int64_t n, int32_t *status)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) mbox[i] = 0;
+    if (i == 0) status[0] = 0;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" size_t sg_pt_split_workspace_bytes(int32_t n_runs, int32_t T)
+{
+    if (n_runs < 1 || T < 2 || T > SG_PT_MAX_T) return 0;
+    return kPtSplitHeader + static_cast<size_t>(n_runs) * 2 * static_cast<size_t>(T) * sizeof(uint64_t);
+}
+
+extern "C" int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, int32_t groups, int32_t waves,
+                               const uint32_t *thr, const uint32_t *thrx, int8_t *spins, int32_t *energy_out,
+                               int32_t *pos, int32_t *emin_trace, uint32_t *swap_acc, void *workspace,
+                               int64_t workspace_bytes, void *stream)
+{
+    const char *who = "sg_pt_run_split";
+    PtJob job;
+    const int rc = pt_prepare(inst, args, thr, thrx, spins, energy_out, pos, emin_trace, swap_acc, who, job);
+    if (rc != SG_OK) return rc;
+    if (groups != 0 && groups != 1 && groups != 2 && groups != 4 && groups != 8)
+        return fail(SG_EINVAL, "%s: groups = %d must be 0, 1, 2, 4 or 8", who, groups);
+    if (groups > 0 && args->T % groups != 0)
+        return fail(SG_EINVAL, "%s: T = %d is not a multiple of groups = %d", who, args->T, groups);
+    if (waves != 0 && waves != 4 && waves != 8 && waves != 12 && waves != 16)
+        return fail(SG_EINVAL, "%s: waves = %d must be 0, 4, 8, 12 or 16", who, waves);
+    if (groups == 0) {
+        // the most groups per run (dividing T) whose launch has at most one
+        // work group per compute unit
+        int dev = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(SG_EDEVICE, "%s: device query failed", who);
+        const int64_t chunks = (static_cast<int64_t>(args->n_runs) + 7) / 8;
+        groups = 1;
+        for (int gg : {2, 4, 8})
+            if (args->T % gg == 0 && chunks * 8 * gg <= n_cu) groups = gg;
+    }
+    const uint32_t k0 = static_cast<uint32_t>(args->seed), k1 = static_cast<uint32_t>(args->seed >> 32);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t need = sg_pt_split_workspace_bytes(args->n_runs, args->T);
+    if (groups > 1 || workspace) {
+        if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 7u) != 0)
+            return fail(SG_EINVAL, "%s: workspace must be a non-NULL 8-byte aligned device pointer", who);
+        if (workspace_bytes < 0 || static_cast<size_t>(workspace_bytes) < need)
+            return fail(SG_EINVAL, "%s: workspace of %lld bytes, %zu needed", who,
+                        static_cast<long long>(workspace_bytes), need);
+    }
+    job.status = static_cast<int32_t *>(workspace);
+    job.mbox = workspace ? reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + kPtSplitHeader) : nullptr;
+    clear_error();
+    // the mailbox (split form only) and the status word are cleared first
+    const int64_t n = groups > 1 ? static_cast<int64_t>(args->n_runs) * 2 * args->T : 0;
+    (void)hipGetLastError();
+    if (workspace)
+        hipLaunchKernelGGL(k_pt_split_clear, dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + 255) / 256))),
+                           dim3(256), 0, st, job.mbox, n, job.status);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(SG_EDEVICE, "%s: clear launch failed: %s", who, hipGetErrorString(err));
+    if (groups == 1) return pt_dispatch<false>(inst->L, job, args->n_runs, waves ? waves : pt_waves(inst->L, args->T),
+                                               k0, k1, st, who);
+    job.G = groups;
+    const int nw = waves ? waves : pt_split_waves(args->T / groups * inst->L * inst->L / 2);
+    return pt_dispatch<true>(inst->L, job, args->n_runs, nw, k0, k1, st, who);
+}

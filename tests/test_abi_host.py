@@ -184,3 +184,28 @@ def test_invalid_arguments_are_refused_on_the_host():
     thr = np.zeros(100, np.uint32)
     assert lib.sg_make_thresholds(out.ctypes.data, 4, 25, thr.ctypes.data) == -1
     assert lib.sg_make_instance(6, 3, 1, thr.ctypes.data, thr.ctypes.data, thr.ctypes.data) == -1
+
+
+def test_split_pt_arguments_are_refused_on_the_host():
+    lib = sg.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.sg_pt_split_workspace_bytes(128, 32) == 256 + 128 * 2 * 32 * 8
+    assert lib.sg_pt_split_workspace_bytes(0, 32) == 0 and lib.sg_pt_split_workspace_bytes(4, 65) == 0
+    inst = sg.sg_instance(L=12, J=0x1000, E_gs=-10)
+    args = sg.sg_pt_args(n_runs=4, T=6, n_steps=10, K=24, M=8, init_random=1, seed=1)
+    need = lib.sg_pt_split_workspace_bytes(4, 6)
+
+    def call(groups, waves, ws, nbytes):
+        return _bad_call(lib.sg_pt_run_split, ctypes.byref(inst), ctypes.byref(args), groups, waves, fake, fake,
+                         fake, fake, fake, None, None, ws, nbytes, None)
+    for groups, waves, ws, nbytes, text in ((3, 0, fake, need, "groups = 3"),
+                                           (4, 0, fake, need, "multiple"),
+                                           (2, 5, fake, need, "waves = 5"),
+                                           (2, 0, None, 0, "workspace"),
+                                           (2, 0, fake, need - 8, "needed"),
+                                           (2, 0, ctypes.c_void_p(0x1004), need, "aligned")):
+        rc, msg = call(groups, waves, ws, nbytes)
+        assert rc == -1 and text in msg, (groups, waves, msg)
+    args.T = 1
+    rc, msg = call(2, 0, fake, need)
+    assert rc == -1 and "T = 1" in msg
