@@ -64,9 +64,13 @@ constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
 // and the kernel still runs to its end.
 constexpr int kPtPollLimit = 1 << 22;
 
+// Couplings in LDS as E = J + 8 only (F = 8 - J formed in registers): the
+// sweep's LDS reads, not its VALU work, bound the PT step, and storing both
+// halves doubles the coupling reads (measured at L = 8 and 12: E only runs
+// the PT workloads 1.3 to 1.4 times faster).
 template <int L>
 struct PtCfg {
-    static constexpr bool JF = (L <= 12);
+    static constexpr bool JF = false;
 };
 
 // Waves per work group for `units` column units of a colour phase dealt to
@@ -237,19 +241,30 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
     for (int ti = 0; ti < job.n_steps; ++ti) {
         const uint32_t t = static_cast<uint32_t>(job.step0 + ti);
         if constexpr (PREP) {
+            // a unit's energy change over both colours goes to its walker in
+            // one LDS atomic per step (the 64 lanes of a wave mostly share
+            // one walker, so each such atomic is serialised)
+            int32_t acc[UMAX];
+            const uint32_t *tbl[UMAX];
+#pragma unroll
+            for (int i = 0; i < UMAX; ++i) {
+                acc[i] = 0;
+                tbl[i] = s_thr + s_pos[w0 + wks[i]] * kPtThr;
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
 #pragma unroll
                 for (int i = 0; i < UMAX; ++i) {
                     if (!act[i]) continue;
-                    const int wk = w0 + wks[i];
-                    const int32_t dE = Col::template metropolis_unit<true>(
-                        s_spin + wks[i] * G::SPIN_DW, s_j, s_thr + s_pos[wk] * kPtThr, c, un[i],
-                        2u * t + static_cast<uint32_t>(c), k0, k1);
-                    if (dE != 0) atomicAdd(&s_E[wk], dE);
+                    acc[i] += Col::template metropolis_unit<true>(s_spin + wks[i] * G::SPIN_DW, s_j, tbl[i], c, un[i],
+                                                                  2u * t + static_cast<uint32_t>(c), k0, k1);
                 }
-                __syncthreads();
+                if (c == 0) __syncthreads();
             }
+#pragma unroll
+            for (int i = 0; i < UMAX; ++i)
+                if (act[i] && acc[i] != 0) atomicAdd(&s_E[w0 + wks[i]], acc[i]);
+            __syncthreads();
         } else {
             for (int c = 0; c < 2; ++c) {
                 for (int u = tid; u < TG * G::NC; u += NT) {

@@ -7,6 +7,7 @@
 namespace sg {
 
 constexpr size_t kPtSplitHeader = 256;   // status word, padded
+constexpr int kPtSplitMinUnits = 512;
 
 // zeroes the mailbox (tags start at 1) and the status word
 __global__ __launch_bounds__(256) void k_pt_split_clear(uint64_t *mbox, int64_t n, int32_t *status)
@@ -43,7 +44,9 @@ extern "C" int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, 
         return fail(SG_EINVAL, "%s: waves = %d must be 0, 4, 8, 12 or 16", who, waves);
     if (groups == 0) {
         // the most groups per run (dividing T) whose launch has at most one
-        // work group per compute unit
+        // work group per compute unit, while every group keeps at least
+        // kPtSplitMinUnits column units per colour (below that the per-step
+        // exchange of energies outweighs the smaller sweep)
         int dev = 0, n_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -51,7 +54,9 @@ extern "C" int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, 
         const int64_t chunks = (static_cast<int64_t>(args->n_runs) + 7) / 8;
         groups = 1;
         for (int gg : {2, 4, 8})
-            if (args->T % gg == 0 && chunks * 8 * gg <= n_cu) groups = gg;
+            if (args->T % gg == 0 && chunks * 8 * gg <= n_cu &&
+                args->T / gg * inst->L * inst->L / 2 >= kPtSplitMinUnits)
+                groups = gg;
     }
     const uint32_t k0 = static_cast<uint32_t>(args->seed), k1 = static_cast<uint32_t>(args->seed >> 32);
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
 template <int L>
 static int launch_pticm(const PtIcmJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
-    constexpr bool JF = (L <= 12);
+    constexpr bool JF = false;   // E only in LDS: fewer coupling reads (as in PT)
     constexpr size_t kLds = 160 * 1024;
     const size_t base = pticm_lds_bytes<L, JF>(job.T, 1);
     if (base > kLds)
