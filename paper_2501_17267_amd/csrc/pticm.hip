@@ -50,6 +50,92 @@ constexpr size_t pticm_lds_bytes(int T, int ng)
             2 * static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW)) * 4;
 }
 
+// One growth pass over the double column `col` of one slot's cluster: both
+// colour columns of index col, i.e. the sites with x in {2k, 2k+1} at one
+// y, every z.  Its z-links and half of its x-links stay inside it.  The
+// pass reads the cluster bits of the four neighbouring double columns
+// once, then adds, until nothing changes, every disagreeing site (q) joined
+// by a nonzero coupling (nz: [6][SPIN_DW] masks) to a cluster site, inside
+// the item or in those neighbours.  cl is the cluster, laid out like q.
+// Returns 1 if anything was added.  Bits other lanes add meanwhile are seen
+// by a later pass, so the fixpoint of the passes is the connected component
+// of the seed, whatever the order.
+template <int L, bool JF>
+__device__ int icm_grow_column(const uint32_t *q, uint32_t *cl, const uint32_t *nz, int col)
+{
+    using G = Geo<L>;
+    using Col = Column<L, JF>;
+    constexpr int C = G::C, NC = G::NC, SDW = G::SPIN_DW;
+    uint32_t qq[2][C], cc[2][C];
+    uint32_t open = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+            qq[c][m] = q[(c * NC + col) * C + m];
+            cc[c][m] = cl[(c * NC + col) * C + m];
+            open |= qq[c][m] & ~cc[c][m];
+        }
+    if (!open) return 0;   // every disagreeing site here is in already
+    const typename Col::Nbr n = Col::neighbours(0, col);
+    // first what the neighbouring double columns reach (added at once);
+    // ix, nzp, nzm: the nonzero-coupling masks of the links inside the item
+    // (x, +z, -z)
+    uint32_t ix[2][C], nzp[2][C], nzm[2][C];
+    uint32_t first = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t ex = c ? ~n.even_x : n.even_x;   // bytes whose x is even
+        const int oc = c ^ 1;
+#pragma unroll
+        for (int m = 0; m < C; ++m) {
+            const int w = (c * NC + col) * C + m;
+            const uint32_t xp = cl[(oc * NC + n.xp) * C + m], xm = cl[(oc * NC + n.xm) * C + m];
+            const uint32_t yp = cl[(oc * NC + n.yp) * C + m], ym = cl[(oc * NC + n.ym) * C + m];
+            const uint32_t z0 = nz[w], z1 = nz[SDW + w];
+            const uint32_t nw = ((xp & ~ex & z0) | (xm & ex & z1) | (yp & nz[2 * SDW + w]) | (ym & nz[3 * SDW + w])) &
+                                qq[c][m] & ~cc[c][m];
+            cc[c][m] |= nw;
+            first |= nw;
+            ix[c][m] = (z0 & ex) | (z1 & ~ex);
+            nzp[c][m] = nz[4 * SDW + w];
+            nzm[c][m] = nz[5 * SDW + w];
+        }
+    }
+    int added = first != 0;
+    for (;;) {   // ends: every round adds a site or stops
+        uint32_t ch = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t(&S)[C] = cc[c ^ 1];
+#pragma unroll
+            for (int m = 0; m < C; ++m) {
+                uint32_t zp, zm;
+                if (G::TAIL != 0 && m == C - 1)
+                    zp = __builtin_amdgcn_perm(S[0], S[C - 1], 0x00000401u);
+                else
+                    zp = __builtin_amdgcn_alignbyte(S[(m + 1) % C], S[m], 1);
+                if (G::TAIL != 0 && m == 0)
+                    zm = __builtin_amdgcn_perm(S[0], S[C - 1], 0x06050401u);
+                else
+                    zm = __builtin_amdgcn_alignbyte(S[m], S[(m + C - 1) % C], 3);
+                const uint32_t reach = (S[m] & ix[c][m]) | (zp & nzp[c][m]) | (zm & nzm[c][m]);
+                const uint32_t nw = reach & qq[c][m] & ~cc[c][m];
+                cc[c][m] |= nw;
+                ch |= nw;
+            }
+        }
+        if (!ch) break;
+        added = 1;
+    }
+    if (added)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int m = 0; m < C; ++m) cl[(c * NC + col) * C + m] = cc[c][m];
+    return added;
+}
+
 template <int L, bool JF>
 __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0, uint32_t k1)
 {
@@ -212,26 +298,14 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
                 }
             }
             __syncthreads();
-            // growth of every slot's cluster until a pass adds nothing
+            // growth of every slot's cluster until a pass adds nothing; a
+            // work item is one double column of one slot (icm_grow_column)
             int grown = 1;
             while (grown) {
                 int add = 0;
-                for (int p = p0; p < p1; ++p) {
-                    // nothing left to add here: every disagreeing site is in
-                    const uint32_t open = s_q[p] & ~s_cl[p];
-                    if (!open) continue;
-                    const int g = p / SDW, w = p - g * SDW;
-                    const int c = w / (G::NC * G::C), col = (w / G::C) % G::NC, m = w % G::C;
-                    uint32_t nb[6];
-                    Col::nbr_dwords(s_cl + g * SDW, c, col, m, nb);
-                    uint32_t reach = 0;
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) reach |= nb[d] & s_nz[d * SDW + w];
-                    const uint32_t nw = reach & open;
-                    if (nw) {
-                        s_cl[p] |= nw;
-                        add = 1;
-                    }
+                for (int it = tid; it < gn * G::NC; it += NT) {
+                    const int g = it / G::NC;
+                    add |= icm_grow_column<L, JF>(s_q + g * SDW, s_cl + g * SDW, s_nz, it - g * G::NC);
                 }
                 grown = __syncthreads_or(add);
             }
