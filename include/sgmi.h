@@ -176,8 +176,10 @@ int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
 
 /* pt_run with each run spread over `groups` work groups (1, 2, 4 or 8; T a
  * multiple of it; 0 picks the most that keep the launch within one work
- * group per compute unit and give each group at least 512 of the T*L^2/2
- * column units of a colour phase), for fewer runs than the device has compute
+ * group per compute unit and, unless n_runs is below half the compute
+ * units, give each group at least 512 of the T*L^2/2 column units of a
+ * colour phase; with fewer runs it splits only when T*L^3 >= 6144, and
+ * returns 1 when nothing qualifies), for fewer runs than the device has compute
  * units: group g sweeps walkers g*T/groups .. (g+1)*T/groups - 1, and the
  * groups of a run pass their walkers' energies to each other through the
  * workspace once per step, then make the same exchange decisions.  Results

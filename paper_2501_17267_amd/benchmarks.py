@@ -343,8 +343,19 @@ def tuning(a, sg, wl, torch):
     return res
 
 
+def pt_tteps(a, sg, wl, torch):
+    """PT TT-eps versus N (L = 6..12) at eps = 3, 4, 5 % with the tuned ladder
+    (T = 8, beta 0.2 -> 2.0): one run alone (pt_run), one run alone spread
+    over work groups (sg_pt_run_split) and 20 runs per launch."""
+    from . import tuning as tu
+    import sys
+    res = tu.pt_tteps(torch, T=8, beta_max=2.0, log=lambda *m: print("[pt_tteps]", *m, file=sys.stderr, flush=True))
+    res["metric"] = "PT TT-eps vs N at eps = 3, 4, 5% (plain, split, batched)"
+    return res
+
+
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
-          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "fragment_call": fragment_call, "tn": tn, "tuning": tuning,
+          "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "fragment_call": fragment_call, "tn": tn, "tuning": tuning, "pt_tteps": pt_tteps,
           "wide": wide, "pticm": pticm}[name]
     return fn(a, sg, wl, torch)

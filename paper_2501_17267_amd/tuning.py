@@ -19,7 +19,8 @@ pt_tteps       PT (and PT with isoenergetic cluster moves) TT-eps versus N
                per instance one launch of 20 runs with the per-step
                minimum-energy trace; TT-eps = the time of the steps
                needed, from the measured time per step of one run alone
-               (plain) and of the 20-run launch divided by 20 (batched).
+               (plain), of one run alone spread over work groups (split,
+               PT only) and of the 20-run launch divided by 20 (batched).
 """
 from __future__ import annotations
 
@@ -73,10 +74,11 @@ def _pt_tables(T, beta_max):
     return to_device_u32(make_thresholds(beta)), to_device_u32(make_exchange_thresholds(beta, M))
 
 
-def _pt_call(inst, thr, thrx, n_runs, n_steps, seed, icm_from=None, want_trace=False):
-    """PT (icm_from None) or PT with cluster moves from slot icm_from."""
+def _pt_call(inst, thr, thrx, n_runs, n_steps, seed, icm_from=None, want_trace=False, groups=1):
+    """PT (icm_from None; groups as in pt_run) or PT with cluster moves from
+    slot icm_from."""
     if icm_from is None:
-        return pt_run(inst, thr, thrx, n_runs, n_steps, seed, want_trace=want_trace)
+        return pt_run(inst, thr, thrx, n_runs, n_steps, seed, want_trace=want_trace, groups=groups)
     return pticm_run(inst, thr, thrx, n_runs, n_steps, seed, icm_from=icm_from, want_trace=want_trace)
 
 
@@ -142,6 +144,15 @@ def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=
         _pt_call(insts[0], thr, thrx, 1, n_steps, seed, icm_from)
         torch.cuda.synchronize()
         ms_step_plain = (time.perf_counter() - t0) * 1e3 / n_steps
+        ms_step_split = None
+        if icm_from is None:
+            # the same run alone, spread over work groups (sg_pt_run_split)
+            _pt_call(insts[0], thr, thrx, 1, 50, seed, groups=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _pt_call(insts[0], thr, thrx, 1, n_steps, seed, groups=0)
+            torch.cuda.synchronize()
+            ms_step_split = (time.perf_counter() - t0) * 1e3 / n_steps
         steps = {t: [] for t in targets}
         batch_ms = []
         for inst in insts:
@@ -152,6 +163,8 @@ def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=
         ms_step_batched = float(np.mean(batch_ms)) / n_steps / n_runs
         entry = {"N": L ** 3, "ms_per_step_plain": ms_step_plain, "ms_per_step_batched": ms_step_batched,
                  "targets": {}}
+        if ms_step_split is not None:
+            entry["ms_per_step_split"] = ms_step_split
         for t in targets:
             st = steps[t]
             if any(x is None for x in st):
@@ -160,13 +173,16 @@ def pt_tteps(torch, T=32, beta_max=3.0, sizes=(6, 8, 10, 12), n_inst=20, n_runs=
             entry["targets"][str(t)] = {"censored": False, "steps_mean": float(np.mean(st)),
                                         "plain_ms": float(np.mean(st)) * ms_step_plain,
                                         "batched_ms": float(np.mean(st)) * ms_step_batched}
+            if ms_step_split is not None:
+                entry["targets"][str(t)]["split_ms"] = float(np.mean(st)) * ms_step_split
         log(f"pt{'' if icm_from is None else '+icm'} tteps L={L}: {entry}")
         per_L[L] = entry
     fits = {}
     for t in targets:
         pts = [(v["N"], v["targets"][str(t)]) for v in per_L.values() if not v["targets"][str(t)]["censored"]]
-        fits[str(t)] = {form: _fit([N for N, _ in pts], [e[key] for _, e in pts])
-                        for form, key in (("plain", "plain_ms"), ("batched", "batched_ms"))}
+        forms = (("plain", "plain_ms"), ("batched", "batched_ms")) + ((("split", "split_ms"),)
+                                                                    if icm_from is None else ())
+        fits[str(t)] = {form: _fit([N for N, _ in pts], [e[key] for _, e in pts]) for form, key in forms}
     return {"T": T, "beta_max": beta_max, "icm_from": icm_from, "per_L": {str(L): v for L, v in per_L.items()},
             "fits": fits}
 
