@@ -4,8 +4,9 @@ energies, ladder positions, per-step minimum energies, exchange counts) for
 every group count, ragged run counts (not a multiple of the eight runs a
 launch chunk holds), explicit wave counts and resumed runs; at the PT
 workload's full size it equals the one-group pt_run on every run and the
-oracle on a sampled run.  Every call's status word must read 0 (no group gave
-up waiting on another)."""
+oracle on a sampled run; it runs ladders whose walkers do not fit one work
+group's LDS (L = 16, 32 walkers).  Every call's status word must read 0 (no
+group gave up waiting on another)."""
 import numpy as np
 import pytest
 import torch
@@ -47,7 +48,8 @@ def _check_oracle(L, Jo, got, seed, runs, thr, thrx, n_steps, run0=0, step0=0, s
 
 
 @pytest.mark.parametrize("L,T,groups", [(4, 4, 2), (6, 8, 4), (8, 16, 8), (10, 6, 2), (12, 32, 2), (12, 32, 4),
-                                        (14, 12, 4), (16, 8, 2), (12, 32, 0), (8, 5, 0)])
+                                        (14, 12, 4), (16, 8, 2), (12, 32, 0), (8, 5, 0), (8, 8, 0),
+                                        (16, 32, 2), (16, 32, 0)])
 def test_split_bit_exact_against_the_oracle(L, T, groups):
     n_runs, n_steps, seed = 3, 12, 0x5911 + T
     log(f"split PT L={L} T={T} groups={groups} runs={n_runs}")
@@ -121,6 +123,19 @@ def test_split_pt_workload_full_size():
     for k in ("spins", "energy", "pos", "emin_trace", "swap_acc"):
         assert torch.equal(out[k], ref[k]), k
     _check_oracle(w.instance.L, Jo, _host(out), w.seed, [77], thr, thrx, w.n_steps)
+
+
+def test_ladder_beyond_one_groups_lds():
+    # 32 walkers of L = 16 do not fit one work group's LDS: pt_run refuses,
+    # the split form runs them (checked against the oracle above)
+    L, T = 16, 32
+    inst, Jo, go, egs = instance(L, 5, 0)
+    thr, thrx = (dev_u32(a) for a in _ladder(T))
+    with pytest.raises(sg.SgError):
+        sg.pt_run(inst, thr, thrx, 1, 2, 1)
+    out = sg.pt_run(inst, thr, thrx, 1, 2, 1, groups=2)
+    torch.cuda.synchronize()
+    assert _status(out) == 0
 
 
 def test_split_argument_errors():
