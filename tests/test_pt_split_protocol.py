@@ -11,6 +11,7 @@ A variant with a single-half mailbox (no double buffering) shows that the
 check does catch the overwrite the second half prevents."""
 import random
 import threading
+import time
 
 import pytest
 
@@ -19,7 +20,7 @@ def _energy(step, w):
     return (step * 7919 + w * 104729) % 100003 - 50000
 
 
-def _run(T, G, steps, halves, seed, slow0=0.0):
+def _run(T, G, steps, halves, seed, slow0=0.0, wait_s=20.0):
     box = [[(0, 0) for _ in range(T)] for _ in range(halves)]   # (tag, value); zeroed first
     lock = threading.Lock()   # one word's 64-bit access is atomic in the kernel
     seen = [[None] * steps for _ in range(G)]
@@ -43,7 +44,7 @@ def _run(T, G, steps, halves, seed, slow0=0.0):
             for w in range(T):                      # collect
                 if w in mine:
                     continue
-                spins = 0
+                deadline = time.monotonic() + wait_s
                 while True:
                     with lock:
                         t_read, v = box[half][w]
@@ -53,8 +54,7 @@ def _run(T, G, steps, halves, seed, slow0=0.0):
                     if t_read > tag:
                         errors.append(f"group {g} step {ti} walker {w}: tag {t_read} overwrote {tag}")
                         return
-                    spins += 1
-                    if spins > 200000:
+                    if time.monotonic() > deadline:
                         errors.append(f"group {g} step {ti} walker {w}: no word")
                         return
                     if rng.random() < 0.5:
@@ -84,7 +84,7 @@ def test_double_buffered_mailbox_delivers_every_step(T, G, seed):
 def test_single_half_mailbox_is_caught_overwriting():
     # with one half the other groups publish step ti + 1 while group 0 has
     # not yet read step ti: the tag check sees the later tag
-    _, errors = _run(8, 4, 6, 1, 100, slow0=0.05)
+    _, errors = _run(8, 4, 6, 1, 100, slow0=0.05, wait_s=1.0)   # the others then wait in vain
     assert any(e.startswith("group 0") and "overwrote" in e for e in errors), errors[:3]
     # the same lag is harmless with the second half
     seen, errors = _run(8, 4, 6, 2, 100, slow0=0.05)
