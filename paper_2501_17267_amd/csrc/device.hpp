@@ -152,6 +152,13 @@ struct Geo {
     static constexpr int N = L * L * L;
     static constexpr int JDW_EF = 2 * NC * 6 * 2 * C;  // encoded couplings, E and F
     static constexpr int JDW_E = 2 * NC * 6 * C;       // encoded couplings, E only
+    // The odd-stride LDS arrangement of the couplings (kColMajorOdd, with hn
+    // halves per direction): where a column's 6*hn*C dwords sit side by
+    // side (jside: not 4-dword columns, nor hn*C = 2 or 4), the stride from
+    // one column to the next is padded to an odd count; jdw_odd is its size.
+    static constexpr bool jside(int hn) { return C != 4 && hn * C != 2 && hn * C != 4; }
+    static constexpr int jstride_odd(int hn) { return 6 * hn * C + ((6 * hn * C) % 2 == 0 ? 1 : 0); }
+    static constexpr int jdw_odd(int hn) { return 2 * NC * (jside(hn) ? jstride_odd(hn) : 6 * hn * C); }
 };
 
 // The coupling of one direction at four sites of a column dword is encoded

@@ -67,7 +67,8 @@ constexpr int kPtPollLimit = 1 << 22;
 // Couplings in LDS as E = J + 8 only (F = 8 - J formed in registers): the
 // sweep's LDS reads, not its VALU work, bound the PT step, and storing both
 // halves doubles the coupling reads (measured at L = 8 and 12: E only runs
-// the PT workloads 1.3 to 1.4 times faster).
+// the PT workloads 1.3 to 1.4 times faster).  They use the odd-stride
+// arrangement (kColMajorOdd).
 template <int L>
 struct PtCfg {
     static constexpr bool JF = false;
@@ -116,7 +117,7 @@ template <int L, bool JF>
 constexpr size_t pt_lds_bytes(int TG, int T, int mx)
 {
     using G = Geo<L>;
-    return (static_cast<size_t>(TG) * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) +
+    return (static_cast<size_t>(TG) * G::SPIN_DW + G::jdw_odd(JF ? 2 : 1) +
             static_cast<size_t>(T) * kPtThr + 4 * static_cast<size_t>(T) +
             static_cast<size_t>(T - 1) * static_cast<size_t>(mx)) * 4;
 }
@@ -141,9 +142,9 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
 {
     constexpr bool PREP = UMAX > 0;
     using G = Geo<L>;
-    using Col = Column<L, JF>;
+    using Col = Column<L, JF, kColMajor, kColMajorOdd>;
     constexpr int NT = NW * 64;
-    constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
+    constexpr int JDW = G::jdw_odd(JF ? 2 : 1);
     extern __shared__ uint32_t lds[];
     const int T = job.T;
     const int tid = static_cast<int>(threadIdx.x);
@@ -196,7 +197,7 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         if (p < 0 || p >= T) p = tid;  // keeps LDS indices in range; pos must be a permutation
         s_pos[tid] = p;
     }
-    load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
+    load_couplings<L, JF, kColMajorOdd>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
     if (tid < T) s_who[s_pos[tid]] = tid;
     {

@@ -45,7 +45,7 @@ constexpr size_t pticm_lds_bytes(int T, int ng)
 {
     using G = Geo<L>;
     const size_t W = 2 * static_cast<size_t>(T);
-    return (W * G::SPIN_DW + (JF ? G::JDW_EF : G::JDW_E) + static_cast<size_t>(T) * kIcmThr + 3 * W +
+    return (W * G::SPIN_DW + G::jdw_odd(JF ? 2 : 1) + static_cast<size_t>(T) * kIcmThr + 3 * W +
             2 * (static_cast<size_t>(T) - 1) + 2 * static_cast<size_t>(ng) * G::SPIN_DW + 64 +
             2 * static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW)) * 4;
 }
@@ -64,7 +64,7 @@ template <int L, bool JF>
 __device__ int icm_grow_column(const uint32_t *q, uint32_t *cl, const uint32_t *nz, int col)
 {
     using G = Geo<L>;
-    using Col = Column<L, JF>;
+    using Col = Column<L, JF, kColMajor, kColMajorOdd>;
     constexpr int C = G::C, NC = G::NC, SDW = G::SPIN_DW;
     uint32_t qq[2][C], cc[2][C];
     uint32_t open = 0;
@@ -140,9 +140,9 @@ template <int L, bool JF>
 __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
-    using Col = Column<L, JF>;
+    using Col = Column<L, JF, kColMajor, kColMajorOdd>;
     constexpr int NT = kIcmNW * 64;
-    constexpr int JDW = JF ? G::JDW_EF : G::JDW_E;
+    constexpr int JDW = G::jdw_odd(JF ? 2 : 1);
     constexpr int SDW = G::SPIN_DW;
     extern __shared__ uint32_t lds[];
     const int T = job.T, W = 2 * T;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
         s_pos[tid] = p;
     }
     if (tid < 2 * (T - 1)) s_sw[tid] = 0;
-    load_couplings<L, JF>(s_j, job.J, job.jenc, tid, NT);
+    load_couplings<L, JF, kColMajorOdd>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
     if (tid < W) s_who[(tid / T) * T + s_pos[tid]] = tid;
     // the bonds a cluster grows along (nonzero couplings), per dword and

@@ -20,14 +20,14 @@
 
 namespace sg {
 
-enum Layout : int { kColMajor = 0, kDwordMajor = 1 };
+enum Layout : int { kColMajor = 0, kDwordMajor = 1, kColMajorOdd = 2 };
 
 // index of dword m of column col, colour c, in a replica's spin array
 template <int L, int LAY>
 __device__ __forceinline__ int spin_at(int c, int col, int m)
 {
     using G = Geo<L>;
-    return LAY == kColMajor ? (c * G::NC + col) * G::C + m : (c * G::C + m) * G::NC + col;
+    return LAY != kDwordMajor ? (c * G::NC + col) * G::C + m : (c * G::C + m) * G::NC + col;
 }
 
 // index of coupling dword m of column col, colour c, direction d, half h
@@ -43,11 +43,19 @@ __device__ __forceinline__ int spin_at(int c, int col, int m)
 //   otherwise:      all twelve (direction, half) blocks of a column side by
 //                   side; a column stride of 6*HN*C dwords (36, 60, 72 ...)
 //                   already lands successive lanes on distinct banks.
+// kColMajorOdd is kColMajor with that last stride padded to an odd count
+// (19 instead of 18 at L = 12 with E only).  It serves the PT kernels: their
+// sweep is bound by LDS, and at L = 12 the padding made it 2 to 3 % faster;
+// the annealing kernel, bound by VALU, ran 8 % slower with it (E and F,
+// stride 37), so it keeps kColMajor.
 template <int L, int HN>
 __device__ __forceinline__ constexpr int lds_jmode()
 {
     return Geo<L>::C == 4 ? 0 : ((HN * Geo<L>::C == 2 || HN * Geo<L>::C == 4) ? 1 : 2);
 }
+static_assert(Geo<12>::jside(1) && Geo<12>::jstride_odd(1) == 19 && !Geo<16>::jside(1) && !Geo<8>::jside(2) &&
+                  Geo<10>::jside(2),
+              "Geo::jside is mode 2 of lds_jmode");
 
 template <int L, int HN, int LAY>
 __device__ __forceinline__ int coupling_at(int c, int col, int d, int h, int m)
@@ -57,6 +65,7 @@ __device__ __forceinline__ int coupling_at(int c, int col, int d, int h, int m)
     constexpr int mode = lds_jmode<L, HN>();
     if (mode == 0) return (((c * 6 + d) * HN + h) * G::NC + col) * G::C + m;
     if (mode == 1) return ((c * 6 + d) * G::NC + col) * HN * G::C + h * G::C + m;
+    if (LAY == kColMajorOdd) return (c * G::NC + col) * G::jstride_odd(HN) + (d * HN + h) * G::C + m;
     return ((c * G::NC + col) * 6 + d) * HN * G::C + h * G::C + m;
 }
 
@@ -386,7 +395,7 @@ __device__ __forceinline__ void encode_dword(const int8_t *J, int c, int col, in
 
 // Fill the LDS couplings (column-major) from natural-order J[6][N] or from
 // the encoded HBM buffer (dword-major, E and F) when given.
-template <int L, bool JF>
+template <int L, bool JF, int JLAY = kColMajor>
 __device__ void load_couplings(uint32_t *jl, const int8_t *J, const uint32_t *jenc, int tid, int nt)
 {
     using G = Geo<L>;
@@ -406,8 +415,8 @@ __device__ void load_couplings(uint32_t *jl, const int8_t *J, const uint32_t *je
         } else {
             encode_dword<L>(J, c, col, d, m, e, f);
         }
-        jl[coupling_at<L, HN, kColMajor>(c, col, d, 0, m)] = e;
-        if (JF) jl[coupling_at<L, HN, kColMajor>(c, col, d, 1, m)] = f;
+        jl[coupling_at<L, HN, JLAY>(c, col, d, 0, m)] = e;
+        if (JF) jl[coupling_at<L, HN, JLAY>(c, col, d, 1, m)] = f;
     }
 }
 
