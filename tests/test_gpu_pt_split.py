@@ -5,8 +5,9 @@ every group count, ragged run counts (not a multiple of the eight runs a
 launch chunk holds), explicit wave counts and resumed runs; at the PT
 workload's full size it equals the one-group pt_run on every run and the
 oracle on a sampled run; it runs ladders whose walkers do not fit one work
-group's LDS (L = 16, 32 walkers).  Every call's status word must read 0 (no
-group gave up waiting on another)."""
+group's LDS (L = 16, 32 walkers); captured in a hipGraph, every replay equals
+the eager call.  Every call's status word must read 0 (no group gave up
+waiting on another)."""
 import numpy as np
 import pytest
 import torch
@@ -136,6 +137,39 @@ def test_ladder_beyond_one_groups_lds():
     out = sg.pt_run(inst, thr, thrx, 1, 2, 1, groups=2)
     torch.cuda.synchronize()
     assert _status(out) == 0
+
+
+def test_split_pt_captured_in_a_graph_replays_exactly():
+    # the call (mailbox fill kernel + PT kernel) captured once; every replay,
+    # with eager work on the device between replays, equals the eager call
+    L, T, n_runs, n_steps = 8, 16, 13, 20
+    log("split PT graph capture")
+    inst, Jo, go, egs = instance(L, 41, 0)
+    thr, thrx = (dev_u32(a) for a in _ladder(T))
+    ws = torch.empty((sg.pt_split_workspace_bytes(n_runs, T) + 7) // 8, dtype=torch.int64, device="cuda")
+    ref = sg.pt_run(inst, thr, thrx, n_runs, n_steps, 42, want_trace=True, want_swaps=True, groups=4, workspace=ws)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items() if k != "workspace" and v is not None}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):   # warm-up on a side stream before the capture
+        sg.pt_run(inst, thr, thrx, n_runs, n_steps, 42, groups=4, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="relaxed"):
+        out = sg.pt_run(inst, thr, thrx, n_runs, n_steps, 42, want_trace=True, want_swaps=True, groups=4,
+                        workspace=ws)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert _status(out) == 0, rep
+        # (swap_acc is zeroed by a fill kernel captured with the call)
+        for k in ("spins", "energy", "pos", "emin_trace", "swap_acc"):
+            assert torch.equal(out[k], ref[k]), (rep, k)
+        other = sg.pt_run(inst, thr, thrx, 3, 5, 7, groups=2, workspace=ws)   # eager, same workspace
+        torch.cuda.synchronize()
+        assert _status(other) == 0
 
 
 def test_split_argument_errors():
