@@ -366,6 +366,16 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
     }
 }
 
+// Zeroes a split launch's mailbox (n words; tags start at 1) and the status
+// word (a template, so that both entry points' translation units may hold it)
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_pt_split_clear(uint64_t *mbox, int64_t n, int32_t *status)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) mbox[i] = 0;
+    if (i == 0) status[0] = 0;
+}
+
 // Launch T-walker runs with G work groups each (G = 1 without SPLIT) and NW
 // waves per group; `lds_cap` bounds one group's LDS (a fraction of the
 // CU's 160 KB lets several groups share a CU).  SPLIT launches
@@ -407,6 +417,12 @@ static int launch_pt_cfg(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStr
                         per_cu, n_cu);
     }
     (void)hipGetLastError();
+    if (job.status) {
+        // after every check: the mailbox (split form) and the status word
+        const int64_t n = SPLIT ? static_cast<int64_t>(n_runs) * 2 * job.T : 0;
+        hipLaunchKernelGGL(k_pt_split_clear<0>, dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + 255) / 256))),
+                           dim3(256), 0, stream, job.mbox, n, job.status);
+    }
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NW * 64), bytes, stream, job, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "%s: launch failed: %s", who, hipGetErrorString(err));

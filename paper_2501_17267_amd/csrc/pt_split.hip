@@ -10,14 +10,6 @@ constexpr size_t kPtSplitHeader = 256;   // status word, padded
 constexpr int kPtSplitMinUnits = 512;
 constexpr int64_t kPtSplitMinSites = 6144;
 
-// zeroes the mailbox (tags start at 1) and the status word
-__global__ __launch_bounds__(256) void k_pt_split_clear(uint64_t *mbox, int64_t n, int32_t *status)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < n) mbox[i] = 0;
-    if (i == 0) status[0] = 0;
-}
-
 }  // namespace sg
 
 using namespace sg;
@@ -79,14 +71,8 @@ extern "C" int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, 
     job.status = static_cast<int32_t *>(workspace);
     job.mbox = workspace ? reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + kPtSplitHeader) : nullptr;
     clear_error();
-    // the mailbox (split form only) and the status word are cleared first
-    const int64_t n = groups > 1 ? static_cast<int64_t>(args->n_runs) * 2 * args->T : 0;
-    (void)hipGetLastError();
-    if (workspace)
-        hipLaunchKernelGGL(k_pt_split_clear, dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + 255) / 256))),
-                           dim3(256), 0, st, job.mbox, n, job.status);
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return fail(SG_EDEVICE, "%s: clear launch failed: %s", who, hipGetErrorString(err));
+    // the launcher clears the mailbox (split form) and the status word on the
+    // stream, after its own checks, just before the PT kernel
     if (groups == 1) return pt_dispatch<false>(inst->L, job, args->n_runs, waves ? waves : pt_waves(inst->L, args->T),
                                                k0, k1, st, who);
     job.G = groups;
