@@ -295,7 +295,7 @@ def main():
         # let their kernels run side by side (must be set before HIP starts)
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, a.hw_queues))
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

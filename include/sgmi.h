@@ -69,7 +69,7 @@ extern "C" {
 #define SG_ERANGE (-4)       /* value outside what the tables cover */
 #define SG_EBUSY (-5)        /* resource full */
 #define SG_ENOTFOUND (-6)    /* unknown handle or request */
-#define SG_EUNSUPPORTED (-7) /* valid input this build cannot run */
+#define SG_EUNSUPPORTED (-7) /* valid input the library does not support */
 
 #define SG_MAX_L 64          /* largest lattice the kernels accept */
 #define SG_K_MAX 24          /* 6 neighbours x |J| <= 4 */
