@@ -50,7 +50,7 @@ def _check_oracle(L, Jo, got, seed, runs, thr, thrx, n_steps, run0=0, step0=0, s
 
 @pytest.mark.parametrize("L,T,groups", [(4, 4, 2), (6, 8, 4), (8, 16, 8), (10, 6, 2), (12, 32, 2), (12, 32, 4),
                                         (14, 12, 4), (16, 8, 2), (12, 32, 0), (8, 5, 0), (8, 8, 0),
-                                        (16, 32, 2), (16, 32, 0)])
+                                        (16, 32, 2), (16, 32, 0), (8, 64, 8), (6, 64, 2)])
 def test_split_bit_exact_against_the_oracle(L, T, groups):
     n_runs, n_steps, seed = 3, 12, 0x5911 + T
     log(f"split PT L={L} T={T} groups={groups} runs={n_runs}")
