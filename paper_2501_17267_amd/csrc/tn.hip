@@ -579,18 +579,26 @@ int upload(sg_tn_plan &p)
                                 hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess)
             return fail(SG_EDEVICE, "sg_tn_decimate: LDS attribute (%d bytes)", need);
     }
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr;
     if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&side2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-        if (side) (void)hipStreamDestroy(side);
-        if (fork) (void)hipEventDestroy(fork);
-        return fail(SG_EDEVICE, "sg_tn_decimate: side stream");
+        hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&fork2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&join2, hipEventDisableTiming) != hipSuccess) {
+        for (hipStream_t x : {side, side2})
+            if (x) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : {fork, join, fork2, join2})
+            if (x) (void)hipEventDestroy(x);
+        return fail(SG_EDEVICE, "sg_tn_decimate: side streams");
     }
     p.side = side;
     p.fork = fork;
     p.join = join;
+    p.side2 = side2;
+    p.fork2 = fork2;
+    p.join2 = join2;
     p.device = dev;
     return SG_OK;
 }
@@ -669,7 +677,22 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                         k0 = k1;
                     }
             }
+            // a batch of several instances runs as two halves, the second on
+            // the plan's second stream with its own part of the workspace
+            auto range_bytes = [&](const Range &R) {
+                return batch_bytes(int64_t{2} * R.nb * (R.k1 - R.k0), (epre[R.k1] - epre[R.k0]) * R.nb, steps,
+                                   R.k1 - R.k0);
+            };
+            struct Unit { Range a, b; bool pair; };
+            std::vector<Unit> units;
             for (const Range &R : batches) {
+                const Range A{R.b0, R.nb / 2, R.k0, R.k1}, B{R.b0 + R.nb / 2, R.nb - R.nb / 2, R.k0, R.k1};
+                if (R.nb >= 2 && range_bytes(A) + range_bytes(B) <= cap)
+                    units.push_back({A, B, true});
+                else
+                    units.push_back({R, R, false});
+            }
+            auto launch_batch = [&](const Range &R, char *base, hipStream_t bs) {
                 TnBatch bt{};
                 bt.item_hbm0 = P.item0 + P.n_lds;
                 bt.res_k0 = P.n_lds;
@@ -682,7 +705,7 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                 bt.entry_pre = static_cast<const int64_t *>(p.d_entry_pre) + P.hbm0;
                 bt.ents_per_inst = epre[R.k1] - epre[R.k0];
                 const int64_t nt = static_cast<int64_t>(R.nb) * (R.k1 - R.k0) * 2;
-                char *q = heavy;
+                char *q = base;
                 bt.tabs = reinterpret_cast<TnTab *>(q);
                 q += align256(nt * static_cast<int64_t>(sizeof(TnTab)));
                 bt.desc = reinterpret_cast<TnDescX *>(q);
@@ -697,9 +720,9 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                 int max_steps = 0;
                 for (int k = R.k0; k < R.k1; ++k)
                     max_steps = std::max(max_steps, p.shapes[p.items[bt.item_hbm0 + k].shape].n_steps);
-                hipLaunchKernelGGL(k_tn_hbm_prep, dim3(static_cast<uint32_t>((nt * steps + 255) / 256)), dim3(256), 0, st,
+                hipLaunchKernelGGL(k_tn_hbm_prep, dim3(static_cast<uint32_t>((nt * steps + 255) / 256)), dim3(256), 0, bs,
                                    jb, bt);
-                hipLaunchKernelGGL(k_tn_hbm_blocks, dim3(static_cast<uint32_t>((steps + 63) / 64)), dim3(64), 0, st, jb, bt);
+                hipLaunchKernelGGL(k_tn_hbm_blocks, dim3(static_cast<uint32_t>((steps + 63) / 64)), dim3(64), 0, bs, jb, bt);
                 for (int t = 0; t < max_steps; ++t) {
                     // work groups of one (instance, value) at this step: as k_tn_hbm_blocks
                     int64_t blocks_t = 0;
@@ -709,10 +732,25 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                     }
                     if (blocks_t == 0) continue;
                     hipLaunchKernelGGL(k_tn_hbm_step<TROP>, dim3(static_cast<uint32_t>(int64_t{R.nb} * 2 * blocks_t)),
-                                       dim3(kTnThreads), 0, st, bt, wt, t, static_cast<int>(blocks_t));
+                                       dim3(kTnThreads), 0, bs, bt, wt, t, static_cast<int>(blocks_t));
                 }
                 hipLaunchKernelGGL(k_tn_hbm_final<TROP>, dim3(static_cast<uint32_t>((nt + 63) / 64)), dim3(64), 0,
-                                   st, jb, bt);
+                                   bs, jb, bt);
+            };
+            const hipStream_t st2 = static_cast<hipStream_t>(p.side2);
+            for (const Unit &U : units) {
+                if (!U.pair) {
+                    launch_batch(U.a, heavy, st);
+                    continue;
+                }
+                if (hipEventRecord(static_cast<hipEvent_t>(p.fork2), st) != hipSuccess ||
+                    hipStreamWaitEvent(st2, static_cast<hipEvent_t>(p.fork2), 0) != hipSuccess)
+                    return fail(SG_EDEVICE, "sg_tn_decimate: fork");
+                launch_batch(U.a, heavy, st);
+                launch_batch(U.b, heavy + range_bytes(U.a), st2);
+                if (hipEventRecord(static_cast<hipEvent_t>(p.join2), st2) != hipSuccess ||
+                    hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.join2), 0) != hipSuccess)
+                    return fail(SG_EDEVICE, "sg_tn_decimate: join");
             }
         }
         if (both && hipStreamWaitEvent(st, static_cast<hipEvent_t>(p.join), 0) != hipSuccess)
@@ -761,12 +799,14 @@ int sg_tn_plan_destroy(sg_tn_plan *p)
 {
     if (!p) return fail(SG_EINVAL, "sg_tn_plan_destroy: NULL plan");
     clear_error();
-    if (p->side) (void)hipStreamSynchronize(static_cast<hipStream_t>(p->side));
+    for (void *x : {p->side, p->side2})
+        if (x) (void)hipStreamSynchronize(static_cast<hipStream_t>(x));
     for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre})
         if (d) (void)hipFree(d);
-    if (p->side) (void)hipStreamDestroy(static_cast<hipStream_t>(p->side));
-    if (p->fork) (void)hipEventDestroy(static_cast<hipEvent_t>(p->fork));
-    if (p->join) (void)hipEventDestroy(static_cast<hipEvent_t>(p->join));
+    for (void *x : {p->side, p->side2})
+        if (x) (void)hipStreamDestroy(static_cast<hipStream_t>(x));
+    for (void *x : {p->fork, p->join, p->fork2, p->join2})
+        if (x) (void)hipEventDestroy(static_cast<hipEvent_t>(x));
     delete p;
     return SG_OK;
 }

@@ -95,6 +95,10 @@ struct sg_tn_plan {
     // the LDS tier runs beside the workspace tier on a stream of the plan
     // (default priority), forked from and joined to the caller's stream
     void *side = nullptr, *fork = nullptr, *join = nullptr;   // hipStream_t, hipEvent_t x 2
+    // the second half of a workspace-tier batch's instances runs on a
+    // second stream of the plan, so that one half's next step can fill the
+    // device while the other half's step drains
+    void *side2 = nullptr, *fork2 = nullptr, *join2 = nullptr;
 };
 
 namespace sg {
