@@ -374,10 +374,10 @@ typedef struct sg_tn_args {
 /* Decimate n_inst instances with the plan.  SG_EINVAL for bad arguments
  * (including a workspace below the minimum), SG_ERANGE when 2 n_inst times
  * the sites of a phase exceeds one launch (2^31 work groups), SG_ENOMEM
- * when the plan's first upload fails.  Part of the work runs on a stream the plan owns,
+ * when the plan's first upload fails.  Part of the work runs on two streams the plan owns,
  * forked from `stream` and joined back to it within the call's work, so
  * everything stays ordered with respect to `stream`; calls with one plan
- * must not overlap (they share that stream), and the plan must outlive them. */
+ * must not overlap (they share those streams), and the plan must outlive them. */
 int sg_tn_decimate(sg_tn_plan *plan, const sg_tn_args *args, void *stream);
 
 /* Energy (Eq. 1) of n_rep configurations spins [n_rep][N] -> energy [n_rep]. */
