@@ -22,6 +22,50 @@ from . import TnPlan, make_instance, tn_decimate
 from . import workloads as wl
 
 
+def workspace_step_bytes(L, h, n_inst, elem, order=1):
+    """Algorithmic bytes the workspace tier's step kernel moves in one
+    decimation of n_inst instances: for every workspace-tier table (both
+    centre values) and every step, elem bytes per canonical read (none at
+    the first step, two where the eliminated slot is active) and per written
+    entry.  Host only: from the plan's exported programs."""
+    plan = TnPlan(L, h, order)
+    shapes, steps, items = plan.program()
+    lds_bits = plan.info()["lds_max_bits"]
+    plan.close()
+    per_shape = {}
+    total = 0
+    for _, s in items:
+        W, ns, s0 = int(shapes[s][0]), int(shapes[s][1]), int(shapes[s][2])
+        if W <= lds_bits:
+            continue
+        if s not in per_shape:
+            b = 0
+            for t in range(ns):
+                row = steps[s0 + t]
+                a_act, n_base, nm = int(row[8]), int(row[10]), int(row[11]) & 0xFFFFFFFF
+                reads = 0 if t == 0 else (2 if a_act else 1)
+                b += (1 << n_base) * (reads + (1 << bin(nm).count("1"))) * elem
+            per_shape[s] = b
+        total += 2 * per_shape[s]
+    return total * n_inst
+
+
+def study_step_bytes(sizes=(8, 12, 16, 20, 24, 32), n_inst=20, beta_L=12, n_betas=6, n_classes=5):
+    """Algorithmic workspace-step bytes of one run(): (sum-product, tropical).
+    Per size: a one-instance warm-up, the timed one-instance and n_inst-instance
+    calls (sum-product) and one n_inst call (tropical); the beta study at
+    beta_L; the l study at L = 20 (l = 5 is the workspace tier's share); the
+    class study at L = 12 with both forms."""
+    fp = tr = 0
+    for L in sizes:
+        fp += workspace_step_bytes(L, 2, 1 + 1 + n_inst, 8)
+        tr += workspace_step_bytes(L, 2, n_inst, 4)
+    fp += workspace_step_bytes(beta_L, 2, n_betas * n_inst, 8) + workspace_step_bytes(20, 2, n_inst, 8)
+    fp += n_classes * workspace_step_bytes(12, 2, n_inst, 8)
+    tr += n_classes * workspace_step_bytes(12, 2, n_inst, 4)
+    return fp, tr
+
+
 def _batch(torch, L, n):
     specs = wl.tn_instances(L, n)
     Js, egs = [], []

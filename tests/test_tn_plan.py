@@ -217,3 +217,26 @@ def test_workspace_sizes():
 def test_plan_argument_errors(L, h, order, bits):
     with pytest.raises(sg.SgError):
         sg.TnPlan(L, h, order, bits)
+
+
+def test_workspace_step_bytes_accounting():
+    # the algorithmic bytes the bench's TN roofline uses: linear in the
+    # instances, half as many in the tropical form (4-byte entries), and for
+    # one shape equal to a direct count over its exported program
+    from paper_2501_17267_amd import tn_study
+    one = tn_study.workspace_step_bytes(12, 2, 1, 8)
+    assert one > 0 and tn_study.workspace_step_bytes(12, 2, 3, 8) == 3 * one
+    assert 2 * tn_study.workspace_step_bytes(12, 2, 2, 4) == tn_study.workspace_step_bytes(12, 2, 2, 8)
+    plan = sg.TnPlan(12, 2, 1)
+    shapes, steps, items = plan.program()
+    lb = plan.info()["lds_max_bits"]
+    want = 0
+    for _, s in items:
+        W, ns, s0 = (int(v) for v in shapes[s][:3])
+        if W <= lb:
+            continue
+        for t in range(ns):
+            a_act, n_base, nm = int(steps[s0 + t][8]), int(steps[s0 + t][10]), int(steps[s0 + t][11]) & 0xFFFFFFFF
+            reads = 0 if t == 0 else 1 + a_act
+            want += 2 * (reads + 2 ** bin(nm).count("1")) * 2 ** n_base * 8
+    assert one == want
