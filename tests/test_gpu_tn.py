@@ -12,6 +12,8 @@ through the C ABI) against the oracle (oracle/tn.py).
   seconds are checked against it from the decimated configuration.
 * Exact ties: the uniform ferromagnet decimates to all +1 with the first
   phase's scores exactly 0; degenerate single-site fragments.
+* Several instances per call (split into halves on two streams) equal
+  one-instance calls bit for bit.
 """
 import numpy as np
 import pytest
@@ -154,6 +156,23 @@ def test_full_size_run_is_sampled_against_the_oracle():
             r = tn.site_score(L, Js[b], tn.fixed_before(sp[b], ph, int(i)), int(i), h, 2.0)
             assert _close(float(sc[b][i]), r), (b, i, sc[b][i], r)
     log(f"  eps = {[(int(e) - g) / abs(g) for e, g in zip(en, egs)]}")
+
+
+@pytest.mark.parametrize("tropical", [False, True])
+def test_batch_halves_equal_single_instance_calls(tropical):
+    # three instances in the workspace tier run as halves of one and two on
+    # two streams; every instance equals its own one-instance call
+    L, h = 10, 2
+    log(f"tn batch halves L={L} tropical={tropical}")
+    plan = sg.TnPlan(L, h, 1, 8)
+    assert plan.info()["n_hbm_sites"] > 0
+    Js, egs = _instances(L, 3, 7070)
+    sp, en, sc = _run(plan, Js, 2.0, tropical)
+    for b in range(3):
+        sp1, en1, sc1 = _run(plan, [Js[b]], 2.0, tropical)
+        np.testing.assert_array_equal(sp[b], sp1[0])
+        np.testing.assert_array_equal(sc[b], sc1[0])
+        assert en[b] == en1[0]
 
 
 def test_argument_errors():
