@@ -36,7 +36,7 @@ struct PtIcmJob {
     int32_t G;              // slots whose cluster moves run together
 };
 
-constexpr int kIcmNW = 16;          // 1024 lanes per run
+constexpr int kIcmNW = 12;          // 768 lanes per run
 constexpr int kIcmThr = kThrEntries;
 
 // LDS of one run with cluster moves of ng slots at once
