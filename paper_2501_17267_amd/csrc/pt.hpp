@@ -134,6 +134,38 @@ constexpr int pt_umax()
     return (regs / per) < 4 ? regs / per : 4;
 }
 
+// Split form: prepared units per lane whose colour-0 random words of the
+// coming step are drawn while wave 0 waits for the other groups' energies
+// (the words follow from the Philox counter alone, not from the ladder
+// position the exchange settles).  Each holds 4 registers per dword until
+// the sweep.  Counts read off the gfx950 register allocation for L = 4..16:
+// two units at 12 waves and three at 8 spill nothing and keep the work
+// groups a compute unit holds; at 16 waves no register is free, and at 4
+// the extra registers cost L = 10 and 12 a resident work group.
+template <int L, int NW, int UMAX>
+constexpr int pt_npre()
+{
+    constexpr int n = NW == 12 ? 2 : NW == 8 ? 3 : 0;
+    return n < UMAX ? n : UMAX;
+}
+
+// One Metropolis pass over colour 0 of a prepared unit with random words
+// drawn beforehand: the result of Column::metropolis_unit for c = 0.
+template <int L, class Col>
+__device__ __forceinline__ int32_t pt_colour0_drawn(uint32_t *rep, const uint32_t *jl, const uint32_t *thr,
+                                                    const typename Col::Unit &un, const Rand4 (&u)[Col::C])
+{
+    int32_t dE = 0;
+    uint32_t own[Col::C], kb[Col::C];
+    Col::fields_n(rep, jl, 0, un.n.self, un.n, own, kb);
+    const char *tb = reinterpret_cast<const char *>(thr);
+#pragma unroll
+    for (int m = 0; m < Col::C; ++m) own[m] ^= Col::template accept_dword<true>(kb[m], u[m], tb, m, dE);
+#pragma unroll
+    for (int m = 0; m < Col::C; ++m) rep[spin_at<L, kColMajor>(0, un.n.self, m)] = own[m];
+    return dE;
+}
+
 // UMAX: prepared units per lane (0: units are formed at every sweep);
 // WPE: least waves per SIMD the register allocation must allow (0: any).
 template <int L, int NW, bool JF, int UMAX, bool SPLIT, int WPE>
@@ -237,6 +269,19 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         }
     }
     bool dead = false;   // SPLIT: a wait gave up (wave 0 only)
+    constexpr int NPRE = (PREP && SPLIT) ? pt_npre<L, NW, UMAX>() : 0;
+    Rand4 drawn[NPRE > 0 ? NPRE : 1][G::C];   // colour-0 words of the coming step
+    auto draw_colour0 = [&](uint32_t s) {
+        if constexpr (NPRE > 0) {
+#pragma unroll
+            for (int i = 0; i < NPRE; ++i) {
+                const uint64_t q0 = philox_q0(un[i].hp, 2u * s);
+#pragma unroll
+                for (int m = 0; m < G::C; ++m) drawn[i][m] = philox_finish(un[i].pre[m], q0, k0, k1);
+            }
+        }
+    };
+    if (NPRE > 0 && job.n_steps > 0) draw_colour0(static_cast<uint32_t>(job.step0));
 
     // ---- steps ------------------------------------------------------------
     for (int ti = 0; ti < job.n_steps; ++ti) {
@@ -257,8 +302,12 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
 #pragma unroll
                 for (int i = 0; i < UMAX; ++i) {
                     if (!act[i]) continue;
-                    acc[i] += Col::template metropolis_unit<true>(s_spin + wks[i] * G::SPIN_DW, s_j, tbl[i], c, un[i],
-                                                                  2u * t + static_cast<uint32_t>(c), k0, k1);
+                    uint32_t *rep = s_spin + wks[i] * G::SPIN_DW;
+                    if (c == 0 && i < NPRE)
+                        acc[i] += pt_colour0_drawn<L, Col>(rep, s_j, tbl[i], un[i], drawn[i < NPRE ? i : 0]);
+                    else
+                        acc[i] += Col::template metropolis_unit<true>(rep, s_j, tbl[i], c, un[i],
+                                                                      2u * t + static_cast<uint32_t>(c), k0, k1);
                 }
                 if (c == 0) __syncthreads();
             }
@@ -282,15 +331,18 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         }
         if constexpr (SPLIT) {
             // wave 0: publish this group's energies, collect the others',
-            // then exchange; T <= 64 walkers, one lane each
+            // then exchange; T <= 64 walkers, one lane each.  Between the
+            // publishing and the wait every wave draws its colour-0 words of
+            // the next step.
+            const int w = tid;
+            uint64_t *box = job.mbox + (static_cast<int64_t>(run) * 2 + (ti & 1)) * T;
+            const uint32_t tag = static_cast<uint32_t>(ti) + 1u;
+            const bool mine = w >= w0 && w < w0 + TG;
+            if (tid < 64 && mine)
+                __hip_atomic_store(box + w, (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(s_E[w]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (NPRE > 0 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
             if (tid < 64) {
-                const int w = tid;
-                uint64_t *box = job.mbox + (static_cast<int64_t>(run) * 2 + (ti & 1)) * T;
-                const uint32_t tag = static_cast<uint32_t>(ti) + 1u;
-                const bool mine = w >= w0 && w < w0 + TG;
-                if (mine)
-                    __hip_atomic_store(box + w, (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(s_E[w]),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool gave_up = false;
                 if (w < T && !mine && !dead) {
                     uint64_t v = 0;
