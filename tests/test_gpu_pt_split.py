@@ -93,6 +93,26 @@ def test_split_resume_equals_uninterrupted():
         assert torch.equal(full[k], b[k]), k
 
 
+@pytest.mark.parametrize("L,T,groups,waves", [(12, 32, 2, 0), (12, 32, 2, 8), (16, 16, 2, 12)])
+def test_split_resume_with_drawn_colour0_words(L, T, groups, waves):
+    # shapes whose lanes draw the next step's colour-0 words during the
+    # trade (12 waves: up to two units per lane; 8 waves: three, as 1152
+    # units over 512 lanes), resumed at a step other than 0: equal to one
+    # uninterrupted one-group pt_run
+    n_runs, seed = 3, 0x3141
+    log(f"split PT resume with drawn words L={L} T={T} groups={groups} waves={waves}")
+    inst, Jo, go, egs = instance(L, 17, 0)
+    thr, thrx = (dev_u32(a) for a in _ladder(T))
+    ref = sg.pt_run(inst, thr, thrx, n_runs, 15, seed, run0=2)
+    a = sg.pt_run(inst, thr, thrx, n_runs, 6, seed, run0=2, groups=groups, waves=waves)
+    b = sg.pt_run(inst, thr, thrx, n_runs, 9, seed, run0=2, step0=6, spins=a["spins"].clone(),
+                  pos=a["pos"].clone(), groups=groups, waves=waves)
+    torch.cuda.synchronize()
+    assert _status(a) == 0 and _status(b) == 0
+    for k in ("spins", "energy", "pos"):
+        assert torch.equal(b[k], ref[k]), k
+
+
 def test_split_reuses_its_workspace():
     # the mailbox keeps the last call's tags; the next call clears it first
     L, T = 8, 8
