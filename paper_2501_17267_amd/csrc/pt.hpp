@@ -134,14 +134,15 @@ constexpr int pt_umax()
     return (regs / per) < 4 ? regs / per : 4;
 }
 
-// Split form: prepared units per lane whose colour-0 random words of the
-// coming step are drawn while wave 0 waits for the other groups' energies
-// (the words follow from the Philox counter alone, not from the ladder
-// position the exchange settles).  Each holds 4 registers per dword until
-// the sweep.  Counts read off the gfx950 register allocation for L = 4..16:
-// two units at 12 waves and three at 8 spill nothing and keep the work
-// groups a compute unit holds; at 16 waves no register is free, and at 4
-// the extra registers cost L = 10 and 12 a resident work group.
+// Prepared units per lane whose colour-0 random words of the coming step
+// are drawn while wave 0 trades energies with the other groups (split form)
+// or runs the exchange (one group per run); the words follow from the
+// Philox counter alone, not from the ladder position the exchange settles.
+// Each holds 4 registers per dword until the sweep.  Counts read off the
+// gfx950 register allocation for L = 4..16: two units at 12 waves and three
+// at 8 spill nothing and keep the work groups a compute unit holds; at 16
+// waves no register is free, and at 4 the extra registers cost L = 10 and
+// 12 a resident work group.
 template <int L, int NW, int UMAX>
 constexpr int pt_npre()
 {
@@ -269,7 +270,7 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         }
     }
     bool dead = false;   // SPLIT: a wait gave up (wave 0 only)
-    constexpr int NPRE = (PREP && SPLIT) ? pt_npre<L, NW, UMAX>() : 0;
+    constexpr int NPRE = PREP ? pt_npre<L, NW, UMAX>() : 0;
     Rand4 drawn[NPRE > 0 ? NPRE : 1][G::C];   // colour-0 words of the coming step
     auto draw_colour0 = [&](uint32_t s) {
         if constexpr (NPRE > 0) {
@@ -365,6 +366,10 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
                 __builtin_amdgcn_wave_barrier();
             }
         }
+        // one group per run: the waves other than wave 0 draw the next
+        // step's colour-0 words while wave 0 runs the exchange
+        if constexpr (!SPLIT)
+            if (NPRE > 0 && tid >= 64 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
         // exchange of ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ...
         const int k = tid;
         if (k + 1 < T && ((k ^ static_cast<int>(t)) & 1) == 0) {
@@ -397,6 +402,8 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
             for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
             if (lane == 0) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = e;
         }
+        if constexpr (!SPLIT)
+            if (NPRE > 0 && tid < 64 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
         __syncthreads();
     }
 
