@@ -139,14 +139,14 @@ constexpr int pt_umax()
 // or runs the exchange (one group per run); the words follow from the
 // Philox counter alone, not from the ladder position the exchange settles.
 // Each holds 4 registers per dword until the sweep.  Counts read off the
-// gfx950 register allocation for L = 4..16: two units at 12 waves and three
-// at 8 spill nothing and keep the work groups a compute unit holds; at 16
-// waves no register is free, and at 4 the extra registers cost L = 10 and
-// 12 a resident work group.
+// gfx950 register allocation for L = 4..16: two units at 12 waves (one at
+// L = 16) and three at 8 spill nothing and keep the work groups a compute
+// unit holds; at 16 waves no register is free, and at 4 the extra
+// registers cost L = 10 and 12 a resident work group.
 template <int L, int NW, int UMAX>
 constexpr int pt_npre()
 {
-    constexpr int n = NW == 12 ? 2 : NW == 8 ? 3 : 0;
+    constexpr int n = NW == 12 ? (L >= 16 ? 1 : 2) : NW == 8 ? 3 : 0;
     return n < UMAX ? n : UMAX;
 }
 
@@ -276,6 +276,10 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         if constexpr (NPRE > 0) {
 #pragma unroll
             for (int i = 0; i < NPRE; ++i) {
+                // one group per run: lanes without the unit skip it (20.36 ->
+                // 19.91 ms on the PT workload); the split form draws on every
+                // lane, which measured faster there (12.05 against 12.30 ms)
+                if (!SPLIT && !act[i]) continue;
                 const uint64_t q0 = philox_q0(un[i].hp, 2u * s);
 #pragma unroll
                 for (int m = 0; m < G::C; ++m) drawn[i][m] = philox_finish(un[i].pre[m], q0, k0, k1);
