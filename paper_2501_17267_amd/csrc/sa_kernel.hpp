@@ -123,11 +123,14 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
     // Columns held whole in registers: each lane's units (column, replica)
     // are fixed for the anneal, so their neighbour columns and the
     // sweep-independent part of their Philox calls are prepared once.
-    // Only where that state (4 words per dword + 8 per unit) fits in about
-    // 40 registers per lane; shapes with more units per lane keep the
+    // Only where that state (4 words per dword + 8 per unit) fits in the
+    // registers the sweep leaves free: 40 per lane, or 60 at 9 to 12 waves
+    // (three waves per SIMD: such a group has the compute unit's registers
+    // to itself, 168 per lane); shapes with more units per lane keep the
     // per-sweep path.
     constexpr int UPL = (RPW * G::NC + NT - 1) / NT;
-    constexpr bool kPrep = !Col::kStream && UPL * (4 * G::C + 8) <= 40;
+    constexpr int kPrepRegs = (NW >= 9 && NW <= 12) ? 60 : 40;
+    constexpr bool kPrep = !Col::kStream && UPL * (4 * G::C + 8) <= kPrepRegs;
     typename Col::Unit un[kPrep ? UPL : 1];
     int rls[kPrep ? UPL : 1];
     bool act[kPrep ? UPL : 1];
