@@ -29,8 +29,16 @@
  *               meta-heuristic, with fixed-sweep simulated annealing as the
  *               subsystem optimiser on overlapping cubic fragments
  *
- * Parity pins for every function live in tests/test_oracle_*.py; no function
- * here is "parity unpinned".
+ * Parity pins for every function live in tests/test_oracle_*.py.  One part
+ * is "parity unpinned": the 64-bit finaliser of orc_sm64_next (its
+ * multipliers and shifts).  No published known-answer output of splitmix64
+ * is available to test it against, and the Weyl-sequence test holds for any
+ * finaliser.  A wrong finaliser would change which stand-in instance a seed
+ * draws, not whether the instance is valid: the planting, class and
+ * brute-force pins check validity for whatever stream is drawn.
+ *
+ * The conventions fixed here (counter layouts, seed orders, phase orders)
+ * are frozen: a change to them names the reading it follows and adds a pin.
  */
 #ifndef ORACLE_H
 #define ORACLE_H

@@ -106,8 +106,9 @@ def test_planted_state_is_gauge_scrambled():
 
 
 def test_random_configurations_average_epsilon_one():
-    # P:72-style baseline: a uniformly random configuration has E[E] = 0, so
-    # E[eps] = 1; check the sample mean against a CLT bound
+    # the random-configuration baseline of Sec. I.A (about 100 % off): a
+    # uniformly random configuration has E[E] = 0, so E[eps] = 1; check the
+    # sample mean against a CLT bound
     L = 8
     J, g, egs = oracle.make_instance(L, 6, 31)
     n = 2000
@@ -118,3 +119,62 @@ def test_random_configurations_average_epsilon_one():
     eps = np.array([oracle.epsilon(int(e), egs) for e in Es])
     assert abs(eps.mean() - 1.0) < 5.0 * np.sqrt(var_E / n) / abs(egs)
     assert abs(Es.var() / var_E - 1.0) < 0.15
+
+
+def _single_tile_faces(J):
+    """Frustrated faces of the one tile of an open 2x2x2 box, from J alone.
+
+    Site i = x + 2 (y + 2 z).  Each face of the cube is a plaquette of four
+    bonds; it is frustrated when the product of their couplings is negative.
+    The product is invariant under any gauge s_i -> g_i s_i, so the count
+    read from the scrambled J equals the count of the tile as drawn."""
+    def site(x, y, z):
+        return x + 2 * (y + 2 * z)
+
+    def bx(y, z):
+        return int(J[0, site(0, y, z)])
+
+    def by(x, z):
+        return int(J[2, site(x, 0, z)])
+
+    def bz(x, y):
+        return int(J[4, site(x, y, 0)])
+
+    plaquettes = []
+    for x in (0, 1):   # faces normal to x: y- and z-bonds at that x
+        plaquettes.append((by(x, 0), bz(x, 1), by(x, 1), bz(x, 0)))
+    for y in (0, 1):   # normal to y: x- and z-bonds at that y
+        plaquettes.append((bx(y, 0), bz(1, y), bx(y, 1), bz(0, y)))
+    for z in (0, 1):   # normal to z: x- and y-bonds at that z
+        plaquettes.append((bx(0, z), by(1, z), bx(1, z), by(0, z)))
+    return sum(1 for p in plaquettes if np.prod(np.sign(p)) < 0)
+
+
+@pytest.mark.parametrize("cls", [0, 2, 4, 6])
+@pytest.mark.parametrize("seed", [1, 2, 3, 17, 2025])
+def test_tile_class_filter_counts_frustrated_faces(cls, seed):
+    # A 2x2x2 open box holds exactly one tile, so every bond carries one tile
+    # coupling: its twelve couplings are nonzero and in [-2, 2], and the
+    # number of frustrated faces, counted here from J by plaquette products,
+    # is the class the generator was asked for (Sec. II: classes differ by
+    # the frustration of their tiles).
+    J, g, egs = oracle.make_instance(0, cls, seed, dims=(2, 2, 2), periodic=False)
+    bonds = [int(J[0, x + 2 * (y + 2 * z)]) for y in (0, 1) for z in (0, 1) for x in (0,)]
+    bonds += [int(J[2, x + 2 * (0 + 2 * z)]) for x in (0, 1) for z in (0, 1)]
+    bonds += [int(J[4, x + 2 * (y + 0)]) for x in (0, 1) for y in (0, 1)]
+    assert len(bonds) == 12
+    assert all(b != 0 for b in bonds)
+    assert all(abs(b) <= 2 for b in bonds)
+    # no coupling outside the twelve cube edges
+    assert int(np.count_nonzero(J)) == 24
+    assert _single_tile_faces(J) == cls
+
+
+def test_unfiltered_tiles_reach_every_even_face_count():
+    # with no class filter (-1) the draws cover all four possible counts and
+    # never an odd one (every cube has an even number of frustrated faces)
+    seen = set()
+    for seed in range(200):
+        J, g, egs = oracle.make_instance(0, -1, seed, dims=(2, 2, 2), periodic=False)
+        seen.add(_single_tile_faces(J))
+    assert seen == {0, 2, 4, 6}

@@ -3,7 +3,10 @@
 * Philox4x32-10: against rocRAND's open-source engine (an independent
   implementation, compiled here as host code), through both its raw rounds
   and its public seed/subsequence/offset interface.
-* splitmix64: against the closed-form Weyl-sequence structure.
+* splitmix64: only its Weyl-sequence structure, which holds for any
+  finaliser.  The finaliser itself is "parity unpinned" (no published
+  known-answer output is available here); it decides which stand-in instance
+  a seed draws, and the generator pins check every drawn instance's validity.
 * Threshold tables: against exp(-beta dE) 2^32 evaluated in 60-digit decimal
   arithmetic (Python's decimal module), which fixes the Metropolis
   acceptance min(1, exp(-beta dE)) of the Boltzmann law (App. A).
