@@ -63,6 +63,9 @@ def lib():
         L.orc_local_field.argtypes = [c.c_int, c.c_int, c.c_int, i8p, i8p, c.c_int64]
         L.orc_epsilon.restype = c.c_double
         L.orc_epsilon.argtypes = [c.c_int64, c.c_int64]
+        L.orc_eps_stats.restype = c.c_int
+        L.orc_eps_stats.argtypes = [i32p, c.c_int, c.c_int, i64p, f64p, c.c_int, c.c_double, c.c_int,
+                                    i64p, i32p, i32p, i32p, c.c_void_p]
         L.orc_schedule.restype = c.c_int
         L.orc_schedule.argtypes = [c.c_int, c.c_double, c.c_double, c.c_int, f64p]
         L.orc_thresholds.restype = c.c_int
@@ -148,6 +151,33 @@ def local_field(J, s, dims, i: int) -> int:
 
 def epsilon(E: int, E_gs: int) -> float:
     return float(lib().orc_epsilon(int(E), int(E_gs)))
+
+
+def eps_stats(energy, E_gs, targets=(), eps_max: float = 1.0, n_bins: int = 0):
+    """Per-group optimality-gap statistics (orc_eps_stats).  energy: int32
+    [n_groups][group_size]; E_gs: one value per group.  Returns a dict of
+    NumPy arrays: sum, emin, emax, n_le [n_groups][n_targets] and, when
+    n_bins > 0, hist [n_groups][n_bins]."""
+    e = np.ascontiguousarray(energy, np.int32)
+    if e.ndim == 1:
+        e = e[None, :]
+    G, n = e.shape
+    gs = np.ascontiguousarray(np.broadcast_to(np.asarray(E_gs, np.int64), (G,)))
+    tg = np.ascontiguousarray(np.asarray(targets, np.float64).reshape(-1))
+    if tg.size == 0:
+        tg_arr = np.zeros(1, np.float64)
+    else:
+        tg_arr = tg
+    out = {"sum": np.zeros(G, np.int64), "emin": np.zeros(G, np.int32), "emax": np.zeros(G, np.int32),
+           "n_le": np.zeros((G, max(1, tg.size)), np.int32)}
+    hist = np.zeros((G, n_bins), np.uint32) if n_bins > 0 else None
+    _check(lib().orc_eps_stats(e, G, n, gs, tg_arr, int(tg.size), float(eps_max), int(n_bins),
+                               out["sum"], out["emin"], out["emax"], out["n_le"],
+                               hist.ctypes.data if hist is not None else None), "orc_eps_stats")
+    out["n_le"] = out["n_le"][:, :tg.size]
+    if hist is not None:
+        out["hist"] = hist
+    return out
 
 
 def schedule(kind: int, b0: float, b1: float, S: int) -> np.ndarray:

@@ -297,6 +297,50 @@ double orc_epsilon(int64_t E, int64_t E_gs)
     return ((double)(E - E_gs)) / fabs(gs);
 }
 
+/* The statistics App. D's TT-eps criterion reads off a set of trials: the
+ * mean gap over the trials of an instance (from the exact energy sum), the
+ * extremes, how many trials reach each target, and a histogram of eps. */
+int orc_eps_stats(const int32_t *energy, int n_groups, int group_size, const int64_t *E_gs,
+                  const double *targets, int n_targets, double eps_max, int n_bins,
+                  int64_t *sum, int32_t *emin, int32_t *emax, int32_t *n_le, uint32_t *hist)
+{
+    int g, i, t;
+    if (n_groups < 1 || group_size < 1 || n_targets < 0 || (hist && (n_bins < 1 || !(eps_max > 0.0))))
+        return -1;
+    for (g = 0; g < n_groups; ++g) {
+        const int32_t *e = energy + (int64_t)g * group_size;
+        int64_t total = 0;
+        int32_t lo = e[0], hi = e[0];
+        for (t = 0; t < n_targets; ++t) n_le[g * n_targets + t] = 0;
+        if (hist)
+            for (i = 0; i < n_bins; ++i) hist[(int64_t)g * n_bins + i] = 0;
+        if (E_gs[g] == 0) return -1;
+        for (i = 0; i < group_size; ++i) {
+            double eps = orc_epsilon(e[i], E_gs[g]);
+            total += e[i];
+            if (e[i] < lo) lo = e[i];
+            if (e[i] > hi) hi = e[i];
+            for (t = 0; t < n_targets; ++t)
+                if (eps <= targets[t]) n_le[g * n_targets + t] += 1;
+            if (hist) {
+                double pos = eps / eps_max * (double)n_bins;
+                int b;
+                if (pos < 0.0)
+                    b = 0;
+                else if (pos >= (double)n_bins)
+                    b = n_bins - 1;
+                else
+                    b = (int)floor(pos);
+                hist[(int64_t)g * n_bins + b] += 1;
+            }
+        }
+        sum[g] = total;
+        emin[g] = lo;
+        emax[g] = hi;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* schedules and acceptance tables                                          */
 /* ------------------------------------------------------------------------ */

@@ -77,6 +77,21 @@ int64_t orc_energy(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *s);
 int64_t orc_local_field(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *s, int64_t i);
 double  orc_epsilon(int64_t E, int64_t E_gs);
 
+/* ---- optimality-gap statistics (Eq. 2; App. D's TT-eps criterion) ---------
+ * Groups g = 0..n_groups-1 of group_size consecutive energies (the trials of
+ * one instance).  For each group, with eps_i = orc_epsilon(E_i, E_gs[g]):
+ *   sum[g]   exact sum of the energies (the mean eps over the group is then
+ *            (sum - n E_gs) / (n |E_gs|), one division);
+ *   emin[g], emax[g]  least and greatest energy;
+ *   n_le[g*n_targets + t]  how many eps_i <= targets[t];
+ *   hist[g*n_bins + b]     how many eps_i fall in bin b, where the bin of eps
+ *            is floor(eps / eps_max * n_bins), with negative values in bin 0
+ *            and values at or above eps_max in bin n_bins-1 (nullable).
+ * Returns 0, or -1 on bad input. */
+int orc_eps_stats(const int32_t *energy, int n_groups, int group_size, const int64_t *E_gs,
+                  const double *targets, int n_targets, double eps_max, int n_bins,
+                  int64_t *sum, int32_t *emin, int32_t *emax, int32_t *n_le, uint32_t *hist);
+
 /* ---- schedules and threshold tables ---------------------------------------
  * kind 0: linear  beta_s = b0 + (b1-b0) s/(S-1)
  * kind 1: geometric beta_s = b0 (b1/b0)^(s/(S-1));  S == 1 gives b0. */
