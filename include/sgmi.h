@@ -78,8 +78,8 @@ extern "C" {
  * jenc: optional device buffer of sg_jenc_bytes(L) bytes filled by
  * sg_encode_instance; required for L > SG_LDS_MAX_L (whose couplings are
  * streamed from it during the sweeps), used to speed up the set-up of
- * smaller ones when present.  sa_anneal supports every even L <= 32 and
- * L = 64. */
+ * smaller ones when present.  sa_anneal supports every even L from 4 to
+ * 64. */
 typedef struct sg_instance {
     int32_t L;
     int32_t reserved;
@@ -122,7 +122,7 @@ size_t sg_sa_workspace_bytes(int32_t L, int32_t n_rep);
 int sa_anneal(const sg_instance *inst, const sg_sa_args *args, const uint32_t *thr,
               int8_t *spins, int32_t *energy, int32_t *emin, void *stream);
 
-/* Few replicas of a large lattice (L = 26..32 and 64), spread over the
+/* Few replicas of a large lattice (even L = 26..64), spread over the
  * whole device.  The method is that of sa_anneal (App. D sweeps, same
  * counters, same result), but each colour phase of each sweep is one
  * launch with one lane per column dword of every replica, instead of one
@@ -387,6 +387,37 @@ int energy(const sg_instance *inst, int32_t n_rep, const int8_t *spins, int32_t 
 /* Optimality gap (Eq. 2): eps[i] = (energy[i] - E_gs) / |E_gs| in double,
  * from exact integers.  energy and eps_out are device arrays of n entries. */
 int epsilon(const int32_t *energy, int64_t n, int64_t E_gs, double *eps_out, void *stream);
+
+/* Optimality-gap statistics per instance (Eq. 2, and the TT-eps criterion
+ * of App. D: a target is reached when the mean gap over an instance's
+ * trials is at or below it).  energy: device int32 [n_groups][group_size],
+ * the trials of group g contiguous; E_gs: device int64 [n_groups], nonzero.
+ * With eps_i = (E_i - E_gs[g]) / |E_gs[g]| in double from exact integers
+ * (as epsilon()), stats_out[g] (device) receives the exact energy sum (so
+ * the mean gap is (sum - n E_gs) / (n |E_gs|)), the least and greatest
+ * energy, and n_le[t] = the number of trials with eps_i <= targets[t] for
+ * the n_targets (0..SG_EPS_MAX_TARGETS) host values targets[].  hist_out
+ * (device uint32 [n_groups][n_bins], nullable; n_bins 1..SG_EPS_MAX_BINS,
+ * eps_max > 0) counts the trials per bin floor(eps_i / eps_max * n_bins),
+ * negative gaps in bin 0 and gaps at or above eps_max in bin n_bins-1.
+ * One work group per group; the outputs are overwritten, not added to.
+ * SG_EINVAL for bad shapes or pointers; an E_gs entry of 0 gives a
+ * division by zero (inf/nan gaps), not an error, since E_gs is not read on
+ * the host. */
+#define SG_EPS_MAX_TARGETS 8
+#define SG_EPS_MAX_BINS 1024
+typedef struct sg_eps_stats {
+    int64_t energy_sum;
+    int32_t energy_min;
+    int32_t energy_max;
+    int32_t n;                           /* group_size */
+    int32_t n_le[SG_EPS_MAX_TARGETS];    /* entries past n_targets are 0 */
+    int32_t reserved;
+} sg_eps_stats;
+
+int epsilon_stats(const int32_t *energy, int32_t n_groups, int32_t group_size, const int64_t *E_gs,
+                  const double *targets, int32_t n_targets, double eps_max, int32_t n_bins,
+                  sg_eps_stats *stats_out, uint32_t *hist_out, void *stream);
 
 /* ---- launch shapes and autotuning -----------------------------------------------
  * The annealing kernel exists in several launch shapes per lattice size

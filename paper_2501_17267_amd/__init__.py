@@ -92,6 +92,15 @@ class sg_sa_tune_result(ctypes.Structure):
                 ("attempts_per_s", ctypes.c_double)]
 
 
+SG_EPS_MAX_TARGETS = 8
+SG_EPS_MAX_BINS = 1024
+
+
+class sg_eps_stats(ctypes.Structure):
+    _fields_ = [("energy_sum", ctypes.c_int64), ("energy_min", ctypes.c_int32), ("energy_max", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("n_le", ctypes.c_int32 * SG_EPS_MAX_TARGETS), ("reserved", ctypes.c_int32)]
+
+
 class sg_pt_args(ctypes.Structure):
     _fields_ = [("n_runs", ctypes.c_int32), ("run0", ctypes.c_uint32),
                 ("T", ctypes.c_int32), ("n_steps", ctypes.c_int32),
@@ -160,6 +169,7 @@ def lib() -> ctypes.CDLL:
     L.sg_tn_workspace_bytes.restype = c.c_int64
     L.sg_tn_decimate.argtypes = [vp, c.POINTER(sg_tn_args), vp]
     L.epsilon.argtypes = [vp, c.c_int64, c.c_int64, vp, vp]
+    L.epsilon_stats.argtypes = [vp, c.c_int32, c.c_int32, vp, vp, c.c_int32, c.c_double, c.c_int32, vp, vp, vp]
     L.sg_batch_create.argtypes = [vp, c.c_int32, c.c_int32, c.POINTER(c.c_void_p)]
     L.sg_batch_launch.argtypes = [vp, vp]
     L.sg_batch_info.argtypes = [vp, vp, vp, vp]
@@ -647,6 +657,40 @@ def epsilon(energy_t, E_gs: int, stream=None):
     _check(lib().epsilon(_dptr(energy_t, "energy"), n, int(E_gs), _dptr(out, "eps"),
                          _stream(stream)), "epsilon")
     return out
+
+
+def epsilon_stats(energy_t, E_gs, targets=(), eps_max: float = 1.0, n_bins: int = 0, stream=None):
+    """Per-instance gap statistics on the device (epsilon_stats).  energy_t:
+    int32 [n_groups][group_size] (or 1-D: one group); E_gs: an int or a
+    sequence of n_groups ints.  Returns device tensors: ``sum`` int64,
+    ``emin``, ``emax`` int32, ``n_le`` int32 [n_groups][n_targets] and, with
+    n_bins > 0, ``hist`` int32 bits of uint32 counts [n_groups][n_bins]."""
+    import torch
+    e = energy_t if energy_t.dim() == 2 else energy_t.reshape(1, -1)
+    G, n = int(e.shape[0]), int(e.shape[1])
+    gs_host = np.broadcast_to(np.asarray(E_gs, np.int64), (G,))
+    gs = torch.from_numpy(np.array(gs_host, np.int64)).to(e.device)
+    tg = np.ascontiguousarray(np.asarray(targets, np.float64).reshape(-1))
+    raw = torch.empty((G, ctypes.sizeof(sg_eps_stats) // 4), dtype=torch.int32, device=e.device)
+    hist = torch.empty((G, n_bins), dtype=torch.int32, device=e.device) if n_bins > 0 else None
+    _check(lib().epsilon_stats(_dptr(e, "energy"), G, n, _dptr(gs, "E_gs"),
+                               ctypes.c_void_p(tg.ctypes.data) if tg.size else None, int(tg.size),
+                               float(eps_max), int(n_bins), _dptr(raw, "stats"), _dptr(hist, "hist"),
+                               _stream(stream)), "epsilon_stats")
+    out = {"sum": raw[:, 0:2].contiguous().view(torch.int64).reshape(G), "emin": raw[:, 2], "emax": raw[:, 3],
+           "n_le": raw[:, 5:5 + tg.size], "n": n}
+    if hist is not None:
+        out["hist"] = hist
+    return out
+
+
+def mean_epsilon(stats: dict, E_gs) -> np.ndarray:
+    """Mean gap per group from the exact energy sums of epsilon_stats (host
+    NumPy, one division per group): (sum - n E_gs) / (n |E_gs|)."""
+    s = stats["sum"].cpu().numpy().astype(np.int64)
+    n = int(stats["n"])
+    gs = np.broadcast_to(np.asarray(E_gs, np.int64), s.shape)
+    return (s - n * gs).astype(np.float64) / (n * np.abs(gs).astype(np.float64))
 
 
 def to_device_u32(a: np.ndarray, device="cuda"):

@@ -50,6 +50,87 @@ __global__ void k_epsilon(const int32_t *E, int64_t n, int64_t E_gs, double *eps
     }
 }
 
+// Per-group gap statistics: one work group per group of trials.  Each lane
+// walks its share of the group's energies (coalesced int32 reads), keeps
+// its sum, extremes and target counts in registers and adds to an LDS
+// histogram; waves combine by shuffles, then one LDS slot per wave.
+constexpr int kStatsThreads = 256;
+
+struct EpsTargets {
+    double t[SG_EPS_MAX_TARGETS];
+};
+
+__global__ __launch_bounds__(kStatsThreads) void k_eps_stats(const int32_t *E, int group_size, const int64_t *E_gs,
+                                                             EpsTargets tg, int n_targets, double eps_max,
+                                                             int n_bins, sg_eps_stats *stats, uint32_t *hist)
+{
+    __shared__ uint32_t s_hist[SG_EPS_MAX_BINS];
+    __shared__ int64_t s_sum[kStatsThreads / 64];
+    __shared__ int32_t s_min[kStatsThreads / 64], s_max[kStatsThreads / 64];
+    __shared__ int32_t s_le[kStatsThreads / 64][SG_EPS_MAX_TARGETS];
+    const int g = static_cast<int>(blockIdx.x);
+    const int tid = static_cast<int>(threadIdx.x);
+    const int32_t *e = E + static_cast<int64_t>(g) * group_size;
+    const int64_t gs = E_gs[g];
+    const double den = fabs(static_cast<double>(gs));
+    if (hist)
+        for (int b = tid; b < n_bins; b += kStatsThreads) s_hist[b] = 0u;
+    __syncthreads();
+    int64_t sum = 0;
+    int32_t lo = 0x7FFFFFFF, hi = static_cast<int32_t>(0x80000000u);
+    int32_t le[SG_EPS_MAX_TARGETS];
+#pragma unroll
+    for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) le[t] = 0;
+    for (int i = tid; i < group_size; i += kStatsThreads) {
+        const int32_t v = e[i];
+        const double eps = static_cast<double>(static_cast<int64_t>(v) - gs) / den;
+        sum += v;
+        lo = min(lo, v);
+        hi = max(hi, v);
+#pragma unroll
+        for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) le[t] += (t < n_targets && eps <= tg.t[t]) ? 1 : 0;
+        if (hist) {
+            const double pos = eps / eps_max * static_cast<double>(n_bins);
+            const int b = pos < 0.0 ? 0 : (pos >= static_cast<double>(n_bins) ? n_bins - 1 : static_cast<int>(pos));
+            atomicAdd(&s_hist[b], 1u);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off, 64);
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+#pragma unroll
+        for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) le[t] += __shfl_xor(le[t], off, 64);
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+        s_sum[wave] = sum;
+        s_min[wave] = lo;
+        s_max[wave] = hi;
+#pragma unroll
+        for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) s_le[wave][t] = le[t];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        sg_eps_stats out;
+        out.energy_sum = 0;
+        out.energy_min = 0x7FFFFFFF;
+        out.energy_max = static_cast<int32_t>(0x80000000u);
+        out.n = group_size;
+        out.reserved = 0;
+        for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) out.n_le[t] = 0;
+        for (int w = 0; w < kStatsThreads / 64; ++w) {
+            out.energy_sum += s_sum[w];
+            out.energy_min = min(out.energy_min, s_min[w]);
+            out.energy_max = max(out.energy_max, s_max[w]);
+            for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) out.n_le[t] += s_le[w][t];
+        }
+        stats[g] = out;
+    }
+    if (hist)
+        for (int b = tid; b < n_bins; b += kStatsThreads) hist[static_cast<int64_t>(g) * n_bins + b] = s_hist[b];
+}
+
 // Encoded couplings (HBM, dword-major so that lanes on adjacent columns
 // read adjacent dwords): for colour c, direction d, half h (E = J + 8,
 // F = 8 - J) and dword m, the dwords of all columns are contiguous.
@@ -146,6 +227,28 @@ int epsilon(const int32_t *energy_in, int64_t n, int64_t E_gs, double *eps_out, 
     hipLaunchKernelGGL(k_epsilon, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0,
                        static_cast<hipStream_t>(stream), energy_in, n, E_gs, eps_out);
     return check_launch("epsilon");
+}
+
+int epsilon_stats(const int32_t *energy_in, int32_t n_groups, int32_t group_size, const int64_t *E_gs,
+                  const double *targets, int32_t n_targets, double eps_max, int32_t n_bins, sg_eps_stats *stats_out,
+                  uint32_t *hist_out, void *stream)
+{
+    if (!energy_in || !E_gs || !stats_out) return fail(SG_EINVAL, "epsilon_stats: NULL energy, E_gs or stats_out");
+    if (n_groups < 1 || group_size < 1)
+        return fail(SG_EINVAL, "epsilon_stats: n_groups = %d, group_size = %d", n_groups, group_size);
+    if (n_targets < 0 || n_targets > SG_EPS_MAX_TARGETS || (n_targets > 0 && !targets))
+        return fail(SG_EINVAL, "epsilon_stats: n_targets = %d (0..%d, targets[] given)", n_targets,
+                    SG_EPS_MAX_TARGETS);
+    if (hist_out && (n_bins < 1 || n_bins > SG_EPS_MAX_BINS || !(eps_max > 0.0)))
+        return fail(SG_EINVAL, "epsilon_stats: histogram needs 1 <= n_bins <= %d and eps_max > 0", SG_EPS_MAX_BINS);
+    EpsTargets tg;
+    for (int t = 0; t < SG_EPS_MAX_TARGETS; ++t) tg.t[t] = t < n_targets ? targets[t] : 0.0;
+    clear_error();
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_eps_stats, dim3(static_cast<unsigned>(n_groups)), dim3(kStatsThreads), 0,
+                       static_cast<hipStream_t>(stream), energy_in, group_size, E_gs, tg, n_targets,
+                       hist_out ? eps_max : 1.0, hist_out ? n_bins : 0, stats_out, hist_out);
+    return check_launch("epsilon_stats");
 }
 
 size_t sg_jenc_bytes(int32_t L)

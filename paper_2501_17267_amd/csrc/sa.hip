@@ -11,51 +11,9 @@
 #include <cstring>
 #include <vector>
 
-#include "variants.hpp"
+#include "sa_launch.hpp"
 
 namespace sg {
-
-template <int L, int RPW, int NW, int JM, bool SL, bool TRACK>
-__global__ __launch_bounds__(NW * 64) void k_sa(const SaJob *jobs, const Group *groups, SaJob inline_job)
-{
-    if (jobs == nullptr) {
-        sa_group<L, RPW, NW, JM, SL, TRACK>(inline_job, static_cast<int>(blockIdx.x), inline_job.k0, inline_job.k1);
-    } else {
-        // groups == NULL: one group per job, job index = block index
-        const Group g = groups ? groups[blockIdx.x] : Group{static_cast<int32_t>(blockIdx.x), 0};
-        const SaJob job = jobs[g.job];
-        sa_group<L, RPW, NW, JM, SL, TRACK>(job, g.group, job.k0, job.k1);
-    }
-}
-
-template <int L, int RPW, int NW, int JM, bool SL>
-static int launch_variant(const SaJob *jobs, const Group *groups, const SaJob &inline_job, int n_groups, bool track,
-                          hipStream_t stream)
-{
-    (void)hipGetLastError();  // clear a stale error so the check below sees this launch only
-    if (track)
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JM, SL, true>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
-                           inline_job);
-    else
-        hipLaunchKernelGGL((k_sa<L, RPW, NW, JM, SL, false>), dim3(n_groups), dim3(NW * 64), 0, stream, jobs, groups,
-                           inline_job);
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return fail(SG_EDEVICE, "annealing kernel launch failed: %s", hipGetErrorString(err));
-    return SG_OK;
-}
-
-template <int L, int JM, bool SL>
-constexpr size_t lds_of(int rpw)
-{
-    using G = Geo<L>;
-    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsEF ? G::JDW_EF : G::JDW_E);
-    return 4 * (((2 * kThrEntries + 3 * rpw + 3) & ~3) + jdw + (SL ? rpw * G::SPIN_DW : 0));
-}
-
-#define SG_VX(L, RPW, NW, JM, SL) \
-    {L, RPW, NW, (JM) == kJLdsE ? 0 : 1, (JM) == kJGlobalEF ? 1 : 0, SL ? 0 : 1, lds_of<L, JM, SL>(RPW), \
-     &launch_variant<L, RPW, NW, JM, SL>}
-#define SG_V(L, RPW, NW, JF) SG_VX(L, RPW, NW, (JF) ? kJLdsEF : kJLdsE, true)
 
 // First entry of each size is its default.  RPW * L^2/2 column units per
 // colour are spread over NW*64 lanes (exactly where the sizes allow).
@@ -87,7 +45,8 @@ static const SaVariant kV28[] = {SG_VX(28, 2, 13, kJGlobalEF, true), SG_VX(28, 1
                                  SG_VX(28, 4, 13, kJGlobalEF, true)};
 static const SaVariant kV30[] = {SG_VX(30, 2, 15, kJGlobalEF, true), SG_VX(30, 1, 8, kJGlobalEF, true)};
 static const SaVariant kV32[] = {SG_VX(32, 2, 16, kJGlobalEF, true), SG_VX(32, 1, 8, kJGlobalEF, true)};
-// couplings and spins both in HBM (a global spin workspace per replica)
+// couplings and spins both in HBM (a global spin workspace per replica);
+// L = 34..62 are in sa_large.hip
 static const SaVariant kV64[] = {SG_VX(64, 1, 16, kJGlobalEF, false), SG_VX(64, 1, 8, kJGlobalEF, false)};
 #undef SG_V
 #undef SG_VX
@@ -102,8 +61,7 @@ const SaVariant *sa_variants(int L, int *n)
         SG_CASE(4) SG_CASE(6) SG_CASE(8) SG_CASE(10) SG_CASE(12) SG_CASE(14) SG_CASE(16) SG_CASE(18)
         SG_CASE(20) SG_CASE(22) SG_CASE(24) SG_CASE(26) SG_CASE(28) SG_CASE(30) SG_CASE(32) SG_CASE(64)
     default:
-        *n = 0;
-        return nullptr;
+        return sa_variants_large(L, n);
     }
 #undef SG_CASE
 }

@@ -25,6 +25,8 @@ struct SaVariant {
 
 // variants of lattice size L (count written to *n); NULL when L has none
 const SaVariant *sa_variants(int L, int *n);
+// variants of the sizes between L = 32 and 64 (sa_large.hip)
+const SaVariant *sa_variants_large(int L, int *n);
 // currently selected variant index of L (default or autotuned)
 int sa_selected(int L);
 

@@ -148,7 +148,7 @@ static int launch_wide(const SaJob &job, hipStream_t st)
     return SG_OK;
 }
 
-bool wide_supported(int L) { return L > SG_LDS_MAX_L && (L <= 32 || L == 64) && lattice_ok(L); }
+bool wide_supported(int L) { return L > SG_LDS_MAX_L && lattice_ok(L); }
 
 size_t wide_bytes(int L, int n_rep)
 {
@@ -163,6 +163,21 @@ int sa_wide(const SaJob &job, int L, hipStream_t st)
     case 28: return launch_wide<28>(job, st);
     case 30: return launch_wide<30>(job, st);
     case 32: return launch_wide<32>(job, st);
+    case 34: return launch_wide<34>(job, st);
+    case 36: return launch_wide<36>(job, st);
+    case 38: return launch_wide<38>(job, st);
+    case 40: return launch_wide<40>(job, st);
+    case 42: return launch_wide<42>(job, st);
+    case 44: return launch_wide<44>(job, st);
+    case 46: return launch_wide<46>(job, st);
+    case 48: return launch_wide<48>(job, st);
+    case 50: return launch_wide<50>(job, st);
+    case 52: return launch_wide<52>(job, st);
+    case 54: return launch_wide<54>(job, st);
+    case 56: return launch_wide<56>(job, st);
+    case 58: return launch_wide<58>(job, st);
+    case 60: return launch_wide<60>(job, st);
+    case 62: return launch_wide<62>(job, st);
     case 64: return launch_wide<64>(job, st);
     default: return fail(SG_EUNSUPPORTED, "sa_anneal (wide): L = %d", L);
     }

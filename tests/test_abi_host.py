@@ -68,14 +68,15 @@ def test_wide_workspace_size():
     # spins of n_rep replicas in the column layout, where the automatic
     # choice takes the multi-work-group path: the selected single-group
     # kernel would launch fewer than 128 replica groups
-    for L in (26, 28, 30, 32, 64):
+    for L in (26, 28, 30, 32, 34, 40, 50, 56, 62, 64):
         C = (L + 3) // 4
         rpw = sg.sa_variants(L)[sg.selected_variant(L)]["replicas_per_group"]
         for n in (1, 3, 16, 127 * rpw, 127 * rpw + 1, 128 * rpw):
             want = n * L * L * C * 4 if -(-n // rpw) < 128 else 0
             assert sg.sa_wide_workspace_bytes(L, n) == want, (L, n)
     assert sg.sa_wide_workspace_bytes(24, 1) == 0
-    assert sg.sa_wide_workspace_bytes(40, 1) == 0
+    assert sg.sa_wide_workspace_bytes(40, 1) == 40 * 40 * 10 * 4
+    assert sg.sa_wide_workspace_bytes(66, 1) == 0
     assert sg.sa_wide_workspace_bytes(32, 0) == 0
 
 
@@ -120,9 +121,16 @@ def test_invalid_arguments_are_refused_on_the_host():
     assert rc == -1 and "workspace" in msg
     assert lib.sg_sa_workspace_bytes(64, 3) == 3 * 2 * 2048 * 16 * 4
     assert lib.sg_sa_workspace_bytes(32, 3) == 0
-    inst.L = 40   # even and in range, but no kernel is built for it
-    assert lib.sa_anneal(ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None) == -7
-    # the multi-work-group path: L = 26..32 and 64 only, with a large enough
+    inst.L = 40   # every even size up to 64 has a kernel; above 32 it needs a workspace
+    rc, msg = _bad_call(lib.sa_anneal, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None)
+    assert rc == -1 and "workspace" in msg
+    assert lib.sg_sa_workspace_bytes(50, 2) == 2 * 2 * (25 * 50) * 13 * 4
+    for L in range(34, 64, 2):
+        assert lib.sg_sa_variants(L, 0, None) >= 1, L
+    inst.L = 66   # beyond SG_MAX_L
+    rc, msg = _bad_call(lib.sa_anneal, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None, None)
+    assert rc == -1 and "L = 66" in msg
+    # the multi-work-group path: even L = 26..64 only, with a large enough
     # 16-byte aligned workspace
     inst.L = 16
     rc, msg = _bad_call(lib.sg_sa_anneal_wide, ctypes.byref(inst), ctypes.byref(args), fake, fake, fake, None)

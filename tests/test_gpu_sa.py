@@ -51,16 +51,25 @@ def test_sa_bit_exact_large_lattices(L):
     _run_and_compare(L, n_rep, 3 if L == 64 else 4, 0xB16 + L, want_emin=True)
 
 
-@pytest.mark.parametrize("L", [26, 28, 30, 32, 64])
+@pytest.mark.parametrize("L", [34, 40, 50, 56, 62])
+def test_sa_bit_exact_paper_scaling_sizes(L):
+    # the sizes of the paper's annealing scaling study (App. D: L = 20 ... 56)
+    # and the ones between 32 and 64: spins in the workspace, couplings from
+    # the encoded image, one replica per work group; L = 34, 50, 62 have the
+    # half-used last column dword (L = 2 mod 4)
+    _run_and_compare(L, 2, 3, 0xC0DE + L, want_emin=True)
+
+
+@pytest.mark.parametrize("L", [26, 28, 30, 32, 34, 40, 50, 56, 64])
 def test_sa_wide_path_bit_exact(L):
     # few replicas without the best-seen energy: sa_anneal spreads each
     # colour phase over the device (one lane per column dword)
-    n_rep = {26: 3, 28: 2, 30: 3, 32: 2, 64: 2}[L]
+    n_rep = {26: 3, 28: 2, 30: 3, 32: 2, 34: 3, 40: 2, 50: 3, 56: 2, 64: 2}[L]
     assert sg.sa_wide_workspace_bytes(L, n_rep) > 0
     _run_and_compare(L, n_rep, 3 if L == 64 else 5, 0xD1DE + L, want_emin=False)
 
 
-@pytest.mark.parametrize("L", [30, 64])
+@pytest.mark.parametrize("L", [30, 50, 64])
 def test_sa_wide_explicit_offsets_resume_and_equality_with_group_kernel(L):
     # explicit wide entry point: replica and sweep offsets, a start from
     # given spins, and equality with the single-work-group kernel
