@@ -198,6 +198,25 @@ int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, int32_t gro
                     int64_t workspace_bytes, void *stream);
 size_t sg_pt_split_workspace_bytes(int32_t n_runs, int32_t T);
 
+/* sg_pt_run_split without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation).  The mailbox lives
+ * in a fixed device array of SG_PT_STATIC_SCRATCH_BYTES bytes inside the
+ * library (one per GPU, held until the process ends), so calls with
+ * sg_pt_split_workspace_bytes(n_runs, T) above that size return SG_ERANGE.
+ * Every other argument, the group choice and the results are those of
+ * sg_pt_run_split.  status_out: device int32 or NULL; it receives 0 after
+ * the call completes, or 1 if a work group gave up waiting on another (the
+ * results are then invalid).  The call clears the array's mailbox on the
+ * stream before its kernel.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (other streams, other threads) race and
+ * must not be issued. */
+#define SG_PT_STATIC_SCRATCH_BYTES (1 << 20)
+int sg_pt_run_split_static(const sg_instance *inst, const sg_pt_args *args, int32_t groups, int32_t waves,
+                           const uint32_t *thr, const uint32_t *thrx, int8_t *spins, int32_t *energy,
+                           int32_t *pos, int32_t *emin_trace, uint32_t *swap_acc, int32_t *status_out,
+                           void *stream);
+
 /* ---- parallel tempering with isoenergetic cluster moves (App. D, PT+ICM) ----
  * The paper only names the cluster moves; this is Houdayer's two-replica
  * move as combined with PT by Zhu, Ochoa and Katzgraber (2015).  Two copies

@@ -157,6 +157,8 @@ def lib() -> ctypes.CDLL:
                                   vp, vp, vp, vp, vp, c.c_int64, vp]
     L.sg_pt_split_workspace_bytes.restype = c.c_size_t
     L.sg_pt_split_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
+    L.sg_pt_run_split_static.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pt_args), c.c_int32, c.c_int32,
+                                         vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.energy.argtypes = [c.POINTER(sg_instance), c.c_int32, vp, vp, vp]
     L.sg_pticm_run.argtypes = [c.POINTER(sg_instance), c.POINTER(sg_pticm_args), vp, vp, vp, vp, vp, vp, vp,
                                vp, vp]

@@ -217,3 +217,19 @@ def test_split_pt_arguments_are_refused_on_the_host():
     args.T = 1
     rc, msg = call(2, 0, fake, need)
     assert rc == -1 and "T = 1" in msg
+
+
+def test_static_split_pt_rejects_runs_beyond_its_array():
+    # the no-allocation split PT refuses, before touching the device, a
+    # mailbox larger than its fixed array (SG_ERANGE), and bad shapes
+    lib = sg.lib()
+    assert lib.sg_pt_split_workspace_bytes(1024, 64) > (1 << 20)
+    args = sg.sg_pt_args(n_runs=1024, run0=0, T=64, n_steps=1, step0=0, K=24, M=1, init_random=1, seed=1)
+    inst = sg.sg_instance(L=8, J=0x1000, jenc=None, E_gs=-10, chain=0)
+    fake = ctypes.c_void_p(0x1000)
+    rc, msg = _bad_call(lib.sg_pt_run_split_static, ctypes.byref(inst), ctypes.byref(args), 0, 0, fake, fake, fake,
+                        fake, fake, None, None, None, None)
+    assert rc == -4 and "static" in msg
+    args.n_runs, args.T = 0, 8
+    assert lib.sg_pt_run_split_static(ctypes.byref(inst), ctypes.byref(args), 0, 0, fake, fake, fake, fake, fake,
+                                      None, None, None, None) == -1
