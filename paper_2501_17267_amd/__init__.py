@@ -670,8 +670,12 @@ def epsilon_stats(energy_t, E_gs, targets=(), eps_max: float = 1.0, n_bins: int 
     import torch
     e = energy_t if energy_t.dim() == 2 else energy_t.reshape(1, -1)
     G, n = int(e.shape[0]), int(e.shape[1])
-    gs_host = np.broadcast_to(np.asarray(E_gs, np.int64), (G,))
-    gs = torch.from_numpy(np.array(gs_host, np.int64)).to(e.device)
+    if isinstance(E_gs, torch.Tensor) and E_gs.is_cuda:
+        assert E_gs.dtype == torch.int64 and E_gs.numel() == G
+        gs = E_gs.contiguous()
+    else:
+        gs_host = np.broadcast_to(np.asarray(E_gs, np.int64), (G,))
+        gs = torch.from_numpy(np.array(gs_host, np.int64)).to(e.device)
     tg = np.ascontiguousarray(np.asarray(targets, np.float64).reshape(-1))
     raw = torch.empty((G, ctypes.sizeof(sg_eps_stats) // 4), dtype=torch.int32, device=e.device)
     hist = torch.empty((G, n_bins), dtype=torch.int32, device=e.device) if n_bins > 0 else None
@@ -691,6 +695,8 @@ def mean_epsilon(stats: dict, E_gs) -> np.ndarray:
     NumPy, one division per group): (sum - n E_gs) / (n |E_gs|)."""
     s = stats["sum"].cpu().numpy().astype(np.int64)
     n = int(stats["n"])
+    if hasattr(E_gs, "cpu"):
+        E_gs = E_gs.cpu().numpy()
     gs = np.broadcast_to(np.asarray(E_gs, np.int64), s.shape)
     return (s - n * gs).astype(np.float64) / (n * np.abs(gs).astype(np.float64))
 
@@ -709,14 +715,19 @@ class SAJob:
     range and schedule, and the output buffers (allocated here)."""
 
     def __init__(self, inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0: int = 0,
-                 spins=None, want_emin: bool = False):
+                 spins=None, want_emin: bool = False, energy=None):
+        """energy: an int32 device tensor of n_rep entries (e.g. a row of a
+        shared [jobs][n_rep] array for epsilon_stats) to receive the final
+        energies; allocated here when None."""
         import torch
         dev = inst.J.device
         self.inst, self.thr, self.n_rep = inst, thr, n_rep
         self.seed, self.rep0, self.sweep0 = seed, rep0, sweep0
         self.init_random = spins is None
         self.spins = torch.empty((n_rep, inst.L ** 3), dtype=torch.int8, device=dev) if spins is None else spins
-        self.energy = torch.empty(n_rep, dtype=torch.int32, device=dev)
+        if energy is not None:
+            assert energy.dtype == torch.int32 and energy.numel() == n_rep and energy.is_contiguous()
+        self.energy = torch.empty(n_rep, dtype=torch.int32, device=dev) if energy is None else energy
         self.emin = torch.empty(n_rep, dtype=torch.int32, device=dev) if want_emin else None
         self.workspace = _workspace(inst.L, n_rep, dev)
 

@@ -160,9 +160,11 @@ def make_stream(rate, duration, seed, p_large=0.05, pool=4, grid=None):
 
 def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool=4, chunk=512,
                 chunk_attempts=1 << 24, p_large=0.05, plain_sample=64, check_sample=32, log=print,
-                instance_seed=None):
-    """Drive a server with a Poisson stream; return latency and throughput."""
-    from . import sa_anneal, epsilon
+                instance_seed=None, return_requests=False):
+    """Drive a server with a Poisson stream; return latency and throughput.
+    return_requests: also return, under "requests_detail", the stream, the
+    instances, tables and the served spins/energies (for checks; not JSON)."""
+    from . import epsilon_stats, mean_epsilon, sa_anneal
     from . import workloads as wl
     total = warmup + duration
     stream = make_stream(rate, total, seed, p_large=p_large, pool=pool)
@@ -214,10 +216,11 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
     wait_ms = (admit - arrive)[meas] * 1e3
     att = (N * stream["S"]).astype(np.float64)
     span = done[meas].max() - (base + warmup)
-    # optimality gap of every served request
+    # optimality gap of every served request (Eq. 2, on the device: one
+    # group of one trial per request)
     en = energy.cpu().numpy().astype(np.int64)
     egs = np.array([insts[(int(L), int(k))].E_gs for L, k in zip(stream["L"], stream["k"])], np.int64)
-    eps = (en - egs) / np.abs(egs)
+    eps = mean_epsilon(epsilon_stats(energy.view(n, 1), egs), egs)
     by_class = {}
     for name, mask in (("small", stream["L"] != LARGE_SIZE), ("large", stream["L"] == LARGE_SIZE)):
         m = meas & mask
@@ -244,7 +247,7 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
     plain_s = time.perf_counter() - p0
     plain_rate = float(att[sample].sum() / plain_s)
     served_rate = float(att[meas].sum() / span)
-    return {
+    out = {
         "metric": "served anneal requests (Poisson stream)", "rate_req_s": rate, "duration_s": duration,
         "warmup_s": warmup, "requests": int(meas.sum()), "completed_all": int(ok.sum()), "submitted": n,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -257,3 +260,7 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
         "kernel_launches": stats["launches"], "set_up_s": t_setup,
         "drain_s": float(end - (base + total)),
     }
+    if return_requests:
+        out["requests_detail"] = {"stream": stream, "off": off, "N": N, "spins": spins, "energy": energy,
+                                  "key": key, "insts": insts, "thr": thr}
+    return out

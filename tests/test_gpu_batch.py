@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2501_17267_amd as sg
 from paper_2501_17267_amd import workloads as wl
 from gpu_util import dev_u32, log, oracle_sa_parallel
@@ -61,4 +62,55 @@ def test_batch_sampled_against_oracle():
         for r in (0, 12):
             np.testing.assert_array_equal(sp[r], ref[3 * k + r][0])
             assert en[r] == ref[3 * k + r][1]
+    b.close()
+
+
+def test_uneven_batch_full_plan_against_oracle():
+    # the uneven workload at its real shape: 4096 instances, L in
+    # {6,8,10,12,16,20}, 64 replicas, budgets {128,256,512,1024}, one
+    # captured plan; replica 0 and replica 63 of three instances of every
+    # (L, budget) pair (72 instances) are compared with the oracle, and the
+    # per-instance gap statistics of all 4096 with the oracle's
+    specs = wl.uneven()
+    seed = wl.uneven_seed()
+    log(f"uneven full plan: {len(specs)} jobs")
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(16) as ex:
+        host = list(ex.map(lambda j: sg.make_instance(j.inst.L, j.inst.cls, j.inst.seed), specs))
+    budgets = sorted({j.n_sweeps for j in specs})
+    thr = {S: sg.make_thresholds(sg.make_schedule(0, 0.1, 3.0, S)) for S in budgets}
+    dthr = {S: dev_u32(t) for S, t in thr.items()}
+    E_all = torch.empty((len(specs), 64), dtype=torch.int32, device="cuda")
+    insts = [sg.Instance(j.inst.L, h[0], h[2], j.inst.chain) for j, h in zip(specs, host)]
+    jobs = [sg.SAJob(inst, dthr[j.n_sweeps], j.n_rep, seed, energy=E_all[k])
+            for k, (inst, j) in enumerate(zip(insts, specs))]
+    b = sg.Batch(jobs, graph=True)
+    b.launch()
+    egs = [i.E_gs for i in insts]
+    st = sg.epsilon_stats(E_all, egs, targets=(0.01, 0.05), eps_max=0.1, n_bins=20)
+    torch.cuda.synchronize()
+    picked = {}
+    for k, j in enumerate(specs):
+        key = (j.inst.L, j.n_sweeps)
+        if len(picked.setdefault(key, [])) < 3:
+            picked[key].append(k)
+    assert len(picked) == 24 and all(len(v) == 3 for v in picked.values())
+    ks = [k for v in picked.values() for k in v]
+
+    def one(k):
+        j = specs[k]
+        sp, en, _ = oracle.sa_run(j.inst.L, host[k][0], seed, j.inst.chain, thr[j.n_sweeps], n_rep=1, rep0=0)
+        sp2, en2, _ = oracle.sa_run(j.inst.L, host[k][0], seed, j.inst.chain, thr[j.n_sweeps], n_rep=1, rep0=63)
+        return k, sp[0], int(en[0]), sp2[0], int(en2[0])
+    log(f"uneven full plan: oracle on {len(ks)} instances x 2 replicas")
+    with cf.ThreadPoolExecutor(16) as ex:
+        for k, s0, e0, s63, e63 in ex.map(one, ks):
+            sp = jobs[k].spins
+            np.testing.assert_array_equal(sp[0].cpu().numpy(), s0, err_msg=f"job {k} replica 0")
+            np.testing.assert_array_equal(sp[63].cpu().numpy(), s63, err_msg=f"job {k} replica 63")
+            assert int(E_all[k, 0]) == e0 and int(E_all[k, 63]) == e63, k
+    ref = oracle.eps_stats(E_all.cpu().numpy(), egs, targets=(0.01, 0.05), eps_max=0.1, n_bins=20)
+    np.testing.assert_array_equal(st["sum"].cpu().numpy(), ref["sum"])
+    np.testing.assert_array_equal(st["n_le"].cpu().numpy(), ref["n_le"])
+    np.testing.assert_array_equal(st["hist"].cpu().numpy().view(np.uint32), ref["hist"])
     b.close()

@@ -6,8 +6,10 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2501_17267_amd as sg
 from paper_2501_17267_amd import serving
+from paper_2501_17267_amd import workloads as wl
 from gpu_util import dev_u32, log
 
 pytestmark = pytest.mark.gpu
@@ -102,3 +104,35 @@ def test_short_poisson_stream():
     log(f"short stream: {res}")
     assert res["served_equals_alone"]
     assert res["completed_all"] == res["submitted"]
+
+
+def test_served_stream_sample_against_oracle():
+    # a short stream with the serving workload's mix (L even 8..32 and 5 %
+    # L = 64, sweeps log-uniform 64..4096, one replica per request): served
+    # requests whose chains the oracle finishes in about a second each are
+    # re-run on the oracle from their own instance, schedule and counters
+    def inst_seed(L, k):
+        return wl.mix64(0xABC000 + 131 * L + k)
+    res = serving.run_poisson(torch, rate=400.0, duration=2.0, warmup=0.0, pool=2, chunk=64,
+                              plain_sample=2, check_sample=2, log=log, p_large=0.05,
+                              instance_seed=inst_seed, return_requests=True)
+    d = res.pop("requests_detail")
+    st, off, N = d["stream"], d["off"], d["N"]
+    cost = N * st["S"]
+    order = np.argsort(cost, kind="stable")
+    small = [int(i) for i in order if st["L"][i] != 64 and cost[i] <= 2e7][:10]
+    large = [int(i) for i in order if st["L"][i] == 64 and cost[i] <= 4e7][:1]
+    sample = small + large
+    log(f"served-vs-oracle sample: {[(int(st['L'][i]), int(st['S'][i])) for i in sample]}")
+    assert len(small) >= 5
+    en = d["energy"].cpu().numpy()
+    for i in sample:
+        L, k, S = int(st["L"][i]), int(st["k"][i]), int(st["S"][i])
+        inst = d["insts"][(L, k)]
+        Jo, _, egs = oracle.make_instance(L, 6, inst_seed(L, k))
+        assert egs == inst.E_gs
+        thr_h = oracle.thresholds(oracle.schedule(0, 0.1, 3.0, S), 24)
+        sp_ref, e_ref, _ = oracle.sa_run(L, Jo, d["key"], inst.chain, thr_h, n_rep=1, rep0=i)
+        got = d["spins"][int(off[i]):int(off[i]) + int(N[i])].cpu().numpy()
+        np.testing.assert_array_equal(got, sp_ref[0], err_msg=f"request {i} L={L} S={S}")
+        assert int(en[i]) == int(e_ref[0]), i

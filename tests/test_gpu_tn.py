@@ -209,3 +209,31 @@ def test_l5_colour_classes_whole_free_fragments():
     J = np.full((6, L ** 3), -1, np.int8)
     spf, enf, _ = _run(plan, [J], 2.0, True)
     assert np.all(spf == 1) and enf[0] == -3 * L ** 3
+
+
+def test_full_size_workspace_tier_sites_per_table_size():
+    # the measured configuration (L = 20, l = 5, beta = 2, wavefront order):
+    # one site of every workspace-tier table size from 2^14 up to 2^20 (the
+    # largest the oracle contracts in about a minute) is compared with the
+    # oracle's marginal, given the decimated spins of the earlier phases
+    import concurrent.futures as cf
+    L, h = 20, 2
+    log(f"tn full size L={L} l=5: workspace-tier sites")
+    plan = sg.TnPlan(L, h, 1)
+    Js, egs = _instances(L, 1, 2020)
+    sp, en, sc = _run(plan, Js, 2.0, False)
+    shapes, _, items = plan.program()
+    W = {int(site): int(shapes[s][0]) for site, s in items}
+    ph = tn.phases(1, L, h)
+    sizes = sorted({w for w in W.values() if 14 <= w <= 20})
+    assert sizes[0] == 14 and sizes[-1] == 20
+    picks = [next(i for i in range(L ** 3) if W[i] == w) for w in sizes]
+    log(f"  table bits {sizes}, sites {picks}")
+
+    def one(i):
+        return i, tn.site_score(L, Js[0], tn.fixed_before(sp[0], ph, int(i)), int(i), h, 2.0)
+    with cf.ThreadPoolExecutor(len(picks)) as ex:
+        for i, r in ex.map(one, picks):
+            log(f"  site {i} W={W[i]}: gpu {sc[0][i]!r} oracle {r!r}")
+            assert _close(float(sc[0][i]), r), (i, W[i], sc[0][i], r)
+            assert sp[0][i] == (1 if r >= 0 else -1)
