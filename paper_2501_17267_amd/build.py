@@ -36,12 +36,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
+def _stale(src: str, newest_header: float) -> bool:
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    return not os.path.exists(obj) or os.path.getmtime(obj) < max(os.path.getmtime(src), newest_header)
+
+
+def build(jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object
+    or than the newest header) and link the library."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
+    if incremental:
+        hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+        hdrs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+        newest = max(os.path.getmtime(h) for h in hdrs)
+        todo = [s for s in srcs if _stale(s, newest)]
+    else:
+        todo = srcs
     jobs = jobs or min(8, len(srcs))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)
@@ -49,4 +64,6 @@ def build(jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else None))
+    inc = "--incremental" in sys.argv
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    print(build(int(args[0]) if args else None, incremental=inc))

@@ -149,6 +149,11 @@ struct Geo {
     static constexpr int C = (L + 3) / 4;        // dwords per column
     static constexpr int TAIL = L % 4;           // valid bytes of the last dword, 0 = 4
     static constexpr int SPIN_DW = 2 * NC * C;   // dwords of one replica
+    // planes of the split column layout: the first CA dwords of a column
+    // (a 64- or 128-bit access) and the other CB
+    static constexpr int CA = C >= 4 ? 4 : (C >= 2 ? 2 : 1);
+    static constexpr int CB = C - CA;
+    static constexpr bool SPLIT_COLUMNS = (C == 3 || C == 5 || C == 6);
     static constexpr int N = L * L * L;
     static constexpr int JDW_EF = 2 * NC * 6 * 2 * C;  // encoded couplings, E and F
     static constexpr int JDW_E = 2 * NC * 6 * C;       // encoded couplings, E only

@@ -22,8 +22,8 @@ static const SaVariant kV4[] = {SG_V(4, 16, 2, true), SG_V(4, 32, 4, true), SG_V
 static const SaVariant kV6[] = {SG_V(6, 32, 3, true), SG_V(6, 32, 9, true), SG_V(6, 64, 9, true)};
 static const SaVariant kV8[] = {SG_V(8, 16, 4, true), SG_V(8, 32, 8, true), SG_V(8, 16, 8, true),
                                 SG_V(8, 1, 1, true)};
-static const SaVariant kV10[] = {SG_V(10, 32, 5, true), SG_V(10, 64, 10, true), SG_V(10, 32, 5, false),
-                                 SG_V(10, 1, 1, true), SG_V(10, 16, 13, true)};
+static const SaVariant kV10[] = {SG_V(10, 5, 4, true), SG_V(10, 32, 5, true), SG_V(10, 64, 10, true),
+                                 SG_V(10, 32, 5, false), SG_V(10, 1, 1, true), SG_V(10, 16, 13, true)};
 static const SaVariant kV12[] = {SG_V(12, 16, 9, true), SG_V(12, 16, 6, true), SG_V(12, 32, 9, true),
                                  SG_V(12, 32, 12, true), SG_V(12, 1, 1, true), SG_V(12, 8, 9, true)};
 static const SaVariant kV14[] = {SG_V(14, 32, 7, false), SG_V(14, 16, 7, true), SG_V(14, 1, 2, true),
@@ -33,8 +33,8 @@ static const SaVariant kV16[] = {SG_V(16, 16, 16, true), SG_V(16, 16, 8, true), 
                                  SG_V(16, 6, 12, true)};
 static const SaVariant kV18[] = {SG_V(18, 8, 7, false), SG_V(18, 8, 11, false), SG_V(18, 1, 3, true),
                                  SG_V(18, 6, 16, false), SG_V(18, 6, 16, true)};
-static const SaVariant kV20[] = {SG_V(20, 8, 5, false), SG_V(20, 4, 5, false), SG_V(20, 1, 4, true),
-                                 SG_V(20, 5, 16, false), SG_V(20, 5, 16, true)};
+static const SaVariant kV20[] = {SG_V(20, 6, 12, true), SG_V(20, 8, 5, false), SG_V(20, 4, 5, false),
+                                 SG_V(20, 1, 4, true), SG_V(20, 5, 16, false), SG_V(20, 5, 16, true)};
 static const SaVariant kV22[] = {SG_V(22, 4, 8, false), SG_V(22, 4, 16, false), SG_V(22, 1, 4, true)};
 static const SaVariant kV24[] = {SG_V(24, 4, 9, false), SG_V(24, 4, 6, false), SG_V(24, 1, 5, false),
                                  SG_V(24, 3, 14, false)};

@@ -44,8 +44,9 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
     constexpr bool JF = (JM != kJLdsE);
-    // LDS arrays column-major, HBM arrays dword-major (coalesced)
-    constexpr int SLAY = SPIN_LDS ? kColMajor : kDwordMajor;
+    // LDS arrays column-major (spin columns of 3, 5 or 6 dwords split in
+    // two planes), HBM arrays dword-major (coalesced)
+    constexpr int SLAY = SPIN_LDS ? (G::SPLIT_COLUMNS ? kColSplit : kColMajor) : kDwordMajor;
     constexpr int JLAY = (JM == kJGlobalEF) ? kDwordMajor : kColMajor;
     using Col = Column<L, JF, SLAY, JLAY>;
     constexpr int NT = NW * 64;
@@ -88,7 +89,7 @@ __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
         s_dE1[tid] = 0;
         s_E[tid] = 0;
     }
-    if (JM != kJGlobalEF) load_couplings<L, JF>(lds + OFF_J, job.J, job.jenc, tid, NT);
+    if (JM != kJGlobalEF) load_couplings<L, JF, JLAY>(lds + OFF_J, job.J, job.jenc, tid, NT);
     __syncthreads();
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);

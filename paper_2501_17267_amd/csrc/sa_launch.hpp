@@ -41,7 +41,7 @@ template <int L, int JM, bool SL>
 constexpr size_t lds_of(int rpw)
 {
     using G = Geo<L>;
-    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsEF ? G::JDW_EF : G::JDW_E);
+    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsE ? G::JDW_E : G::JDW_EF);
     return 4 * (((2 * kThrEntries + 3 * rpw + 3) & ~3) + jdw + (SL ? rpw * G::SPIN_DW : 0));
 }
 

@@ -20,14 +20,26 @@
 
 namespace sg {
 
-enum Layout : int { kColMajor = 0, kDwordMajor = 1, kColMajorOdd = 2 };
+enum Layout : int { kColMajor = 0, kDwordMajor = 1, kColMajorOdd = 2, kColSplit = 3 };
+
+// kColSplit (spins in LDS, columns of C = 3, 5 or 6 dwords): the first CA
+// dwords of every column (CA = 2 or 4) in one plane, CA dwords per column,
+// and the remaining CB = C - CA dwords in a second plane.  A column read is
+// then one 64- or 128-bit access plus one of CB dwords, at lane strides of
+// CA and CB dwords, instead of C dwords at an odd stride.  (Only the spins:
+// the same split of the couplings measured slower than their arrangement
+// below, whose 128-bit reads already spread over the banks.)
 
 // index of dword m of column col, colour c, in a replica's spin array
 template <int L, int LAY>
 __device__ __forceinline__ int spin_at(int c, int col, int m)
 {
     using G = Geo<L>;
-    return LAY != kDwordMajor ? (c * G::NC + col) * G::C + m : (c * G::C + m) * G::NC + col;
+    if (LAY == kDwordMajor) return (c * G::C + m) * G::NC + col;
+    if (LAY == kColSplit)
+        return m < G::CA ? (c * G::NC + col) * G::CA + m
+                         : 2 * G::NC * G::CA + (c * G::NC + col) * G::CB + (m - G::CA);
+    return (c * G::NC + col) * G::C + m;
 }
 
 // index of coupling dword m of column col, colour c, direction d, half h
