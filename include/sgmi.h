@@ -167,7 +167,10 @@ typedef struct sg_pt_args {
  * thrx:       device uint32 [T-1][M] (from sg_make_exchange_thresholds)
  * spins:      device int8 [n_runs][T][N] in/out (walker-major)
  * energy:     device int32 [n_runs][T] out
- * pos:        device int32 [n_runs][T] in/out, walker -> ladder slot
+ * pos:        device int32 [n_runs][T] in/out, walker -> ladder slot; with
+ *             init_random = 0 a run whose pos is not a permutation of
+ *             0..T-1 starts from the identity instead (no LDS index ever
+ *             leaves its range)
  * emin_trace: device int32 [n_runs][n_steps] or NULL: min walker energy after each step
  * swap_acc:   device uint32 [n_runs][T-1] or NULL: accepted exchanges per pair, added to */
 int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
@@ -187,9 +190,11 @@ int pt_run(const sg_instance *inst, const sg_pt_args *args, const uint32_t *thr,
  * 4, 8, 12, 16; 0 picks).  workspace: device memory of
  * sg_pt_split_workspace_bytes(n_runs, T) bytes, 8-byte aligned, owned by the
  * caller; may be NULL only with groups = 1.  The call clears it on the
- * stream first; its first int32 is 0 after the call completes, 1 if a group
- * gave up waiting on another (a group waits at most a few seconds; the
- * results are then invalid).  Calls sharing one workspace must not overlap.
+ * stream first; its first int32 is a status read after the call completes:
+ * 0, or bit 0 set if a group gave up waiting on another (a group waits at
+ * most a few seconds; the results are then invalid), bit 1 set if a run's
+ * pos was not a permutation (the identity was used).  Calls sharing one
+ * workspace must not overlap.
  * SG_EUNSUPPORTED when the launch's work groups would not all be resident on
  * the device at once. */
 int sg_pt_run_split(const sg_instance *inst, const sg_pt_args *args, int32_t groups, int32_t waves,
@@ -205,9 +210,8 @@ size_t sg_pt_split_workspace_bytes(int32_t n_runs, int32_t T);
  * library (one per GPU, held until the process ends), so calls with
  * sg_pt_split_workspace_bytes(n_runs, T) above that size return SG_ERANGE.
  * Every other argument, the group choice and the results are those of
- * sg_pt_run_split.  status_out: device int32 or NULL; it receives 0 after
- * the call completes, or 1 if a work group gave up waiting on another (the
- * results are then invalid).  The call clears the array's mailbox on the
+ * sg_pt_run_split.  status_out: device int32 or NULL; after the call
+ * completes it holds the status word of sg_pt_run_split (0: no problem).  The call clears the array's mailbox on the
  * stream before its kernel.  All calls on one GPU share the array: calls
  * that overlap in time on one GPU (other streams, other threads) race and
  * must not be issued. */
@@ -518,9 +522,10 @@ int sg_batch_destroy(sg_batch *batch);
 /* ---- serving: continuous batching of anneal requests ---------------------------
  * A request anneals one replica of an instance for n_sweeps sweeps with its
  * own schedule rows, seed and replica counter word.  A server thread admits
- * queued requests while the active limit, the memory budget (request state:
- * spins + energy + workspace) and the pool of large-lattice workspaces
- * allow, and advances all active requests in chunks of chunk_sweeps: each
+ * queued requests, in arrival order but passing over (for a bounded time)
+ * one that does not fit yet, while the active limit, the memory budget
+ * (request state: spins + energy + workspace) and the pool of large-lattice
+ * workspaces allow, and advances all active requests in chunks of chunk_sweeps: each
  * lattice size has its own stream, and every time a size's previous chunk
  * finishes, all its active requests -- including those admitted meanwhile --
  * run their next chunk together in one kernel.  A request's result depends
@@ -534,7 +539,9 @@ typedef struct sg_server_config {
     int32_t chunk_sweeps;    /* most sweeps per request per chunk (0: 64) */
     int64_t memory_budget;   /* bytes of admitted request state (0: 8 GiB) */
     int32_t large_slots;     /* preallocated workspaces for lattices above L = 32 */
-    int32_t reserved;
+    int32_t skip_age_ms;     /* a queued request that does not fit is passed over by later
+                                ones while it is younger than this (0: 50 ms); older, it
+                                holds back everything queued after it until it fits */
     int64_t chunk_attempts;  /* > 0: a size's chunk is max(1, min(chunk_sweeps,
                                 chunk_attempts / L^3)) sweeps, so chunks of all sizes
                                 take similar time; 0: chunk_sweeps for every size */
@@ -580,6 +587,11 @@ int sg_server_submit(sg_server *srv, const sg_request *req, uint64_t *id_out);
 int sg_server_poll(sg_server *srv, uint64_t id, sg_request_status *out);
 /* queued: dropped at once; active: retired at its next chunk boundary */
 int sg_server_cancel(sg_server *srv, uint64_t id);
+/* forget a finished (done, cancelled or failed) request: its id becomes
+ * unknown and the server's record of it is freed; SG_EBUSY while it is
+ * queued or active.  A long-running server's callers release every request
+ * once they have read its result. */
+int sg_server_release(sg_server *srv, uint64_t id);
 int sg_server_get_stats(sg_server *srv, sg_server_stats *out);
 /* blocks until no request is queued or active (SG_EBUSY on timeout) */
 int sg_server_wait(sg_server *srv, double timeout_s);

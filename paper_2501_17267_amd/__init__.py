@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "sgmi.h")
 
 SG_OK = 0
 SG_EINVAL = -1
+SG_EBUSY = -5
 SG_MAX_L = 64
 SG_K_MAX = 24
 SG_LDS_MAX_L = 24
@@ -368,15 +369,21 @@ def sa_anneal(inst: Instance, thr, n_rep: int, seed: int, rep0: int = 0, sweep0:
 
 def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0: int = 0,
            step0: int = 0, spins=None, pos=None, want_trace: bool = False,
-           want_swaps: bool = False, stream=None, groups: int = 1, waves: int = 0, workspace=None):
+           want_swaps: bool = False, stream=None, groups: int = 1, waves: int = 0, workspace=None,
+           check: bool = True):
     """Parallel tempering.  thr: device [T][K]; thrx: device [T-1][M].
     groups != 1 (or waves != 0) calls sg_pt_run_split: each run spread over
     that many work groups (0: as many as fill the device), same results;
     workspace: a device tensor of at least pt_split_workspace_bytes(n_runs,
-    T) bytes, allocated here when None.
+    T) bytes, allocated here when None.  pos (with spins) must hold a
+    permutation of the slots per run: checked here, SgError(SG_EINVAL).
+    check (split form, outside stream capture): wait for the call and raise
+    SgError(SG_EBUSY) when a work group gave up waiting on another (the
+    results are then invalid); with check=False, or under capture, the
+    caller reads the status word itself.
     Returns dict(spins [n_runs][T][N], energy [n_runs][T], pos [n_runs][T],
     emin_trace, swap_acc, and for the split form `workspace`, whose first
-    int32 is 1 if a work group gave up waiting on another)."""
+    int32 is the status word: 0, bit 0 a group gave up waiting)."""
     import torch
     dev = inst.J.device
     N = inst.L ** 3
@@ -385,6 +392,10 @@ def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0
     init_random = spins is None
     sp = torch.empty((n_runs, T, N), dtype=torch.int8, device=dev) if init_random else spins
     ps = torch.empty((n_runs, T), dtype=torch.int32, device=dev) if init_random else pos
+    if not init_random:
+        ident = torch.arange(T, dtype=ps.dtype, device=ps.device)
+        if not bool((torch.sort(ps.reshape(n_runs, T), dim=1).values == ident).all()):
+            raise SgError(SG_EINVAL, "pt_run: pos is not a permutation of the ladder slots in every run")
     en = torch.empty((n_runs, T), dtype=torch.int32, device=dev)
     tr = torch.empty((n_runs, n_steps), dtype=torch.int32, device=dev) if want_trace else None
     sw = torch.zeros((n_runs, T - 1), dtype=torch.int32, device=dev) if want_swaps else None
@@ -406,6 +417,11 @@ def pt_run(inst: Instance, thr, thrx, n_runs: int, n_steps: int, seed: int, run0
                                  _dptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
                                  _stream(stream)), "sg_pt_run_split")
     out["workspace"] = workspace
+    if check and not torch.cuda.is_current_stream_capturing():
+        status = int(workspace.view(torch.int32)[0].item())
+        if status & 1:
+            raise SgError(SG_EBUSY, "sg_pt_run_split: a work group gave up waiting on another "
+                                    "(other work held the device); the results are invalid")
     return out
 
 

@@ -53,7 +53,7 @@ struct PtJob {
     int32_t n_runs;
     int32_t G;              // work groups per run (SPLIT)
     uint64_t *mbox;         // [n_runs][2][T] tagged energies (SPLIT)
-    int32_t *status;        // set to 1 when a wait on another group gives up (SPLIT)
+    int32_t *status;        // bit 0: a wait on another group gave up (SPLIT); bit 1: pos was no permutation
 };
 
 constexpr int kPtThr = kThrEntries;  // table entries per ladder slot
@@ -227,12 +227,23 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
         s_E[tid] = 0;
         s_sw[tid] = 0;
         int p = job.init_random ? tid : job.pos[run * T + tid];
-        if (p < 0 || p >= T) p = tid;  // keeps LDS indices in range; pos must be a permutation
+        if (p < 0 || p >= T) p = -1;   // out of range: not a permutation
         s_pos[tid] = p;
+        s_who[tid] = -1;
     }
     load_couplings<L, JF, kColMajorOdd>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
-    if (tid < T) s_who[s_pos[tid]] = tid;
+    if (tid < T && s_pos[tid] >= 0) s_who[s_pos[tid]] = tid;
+    // a pos that is not a permutation of the slots leaves a slot without a
+    // walker: every group of the run then takes the identity instead (so
+    // every LDS index stays in range) and the status word records it
+    if (__syncthreads_or(tid < T && s_who[tid] < 0)) {
+        if (tid < T) {
+            s_pos[tid] = tid;
+            s_who[tid] = tid;
+        }
+        if (tid == 0 && job.status) atomicOr(job.status, 2);
+    }
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
         constexpr int Q = G::N / 4;
@@ -363,7 +374,7 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
                     s_E[w] = static_cast<int32_t>(static_cast<uint32_t>(v));
                 }
                 if (__any(gave_up)) {
-                    if (!dead && w == 0) job.status[0] = 1;
+                    if (!dead && w == 0) atomicOr(job.status, 1);
                     dead = true;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

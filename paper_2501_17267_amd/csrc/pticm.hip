@@ -175,13 +175,21 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     if (tid < W) {
         s_E[tid] = 0;
         int p = job.init_random ? tid % T : job.pos[run * W + tid];
-        if (p < 0 || p >= T) p = tid % T;  // keeps LDS indices in range; pos must be a permutation per copy
+        if (p < 0 || p >= T) p = -1;   // out of range: not a permutation
         s_pos[tid] = p;
+        s_who[tid] = -1;
     }
     if (tid < 2 * (T - 1)) s_sw[tid] = 0;
     load_couplings<L, JF, kColMajorOdd>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
-    if (tid < W) s_who[(tid / T) * T + s_pos[tid]] = tid;
+    if (tid < W && s_pos[tid] >= 0) s_who[(tid / T) * T + s_pos[tid]] = tid;
+    // a copy whose pos is not a permutation of its slots leaves a slot
+    // without a walker: the run then starts from the identity (every LDS
+    // index stays in range)
+    if (__syncthreads_or(tid < W && s_who[tid] < 0) && tid < W) {
+        s_pos[tid] = tid % T;
+        s_who[tid] = tid;
+    }
     // the bonds a cluster grows along (nonzero couplings), per dword and
     // direction, for the whole run
     for (int w = tid; w < SDW; w += NT) {

@@ -23,6 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.hpp"
 #include "variants.hpp"
 
 using namespace sg;
@@ -84,7 +85,8 @@ struct sg_server {
     int device = 0;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<uint64_t> queue;
+    std::deque<AdmitEntry> queue;      // arrival order
+    double skip_age = 0.05;            // seconds a request may be passed over
     std::unordered_map<uint64_t, Request> reqs;
     std::map<int, std::unique_ptr<Lane>> lanes;
     std::vector<void *> ws_pool;
@@ -152,7 +154,7 @@ struct sg_server {
     {
         const double t = steady_now();
         for (size_t i = 0; i < ln.chunk_ids.size(); ++i) {
-            Request &q = reqs[ln.chunk_ids[i]];
+            Request &q = reqs.at(ln.chunk_ids[i]);
             q.in_flight = false;
             q.done += ln.chunk_sweeps[i];
             if (q.done >= q.r.n_sweeps || q.cancel) {
@@ -174,40 +176,37 @@ struct sg_server {
         ln.busy = false;
     }
 
-    // (lock held) admit queued requests that fit
+    // (lock held) admit queued requests that fit (admission.hpp: arrival
+    // order; a request that does not fit is passed over while it is younger
+    // than skip_age)
     bool admit()
     {
-        bool any = false;
-        while (!queue.empty()) {
-            Request &q = reqs[queue.front()];
-            if (q.state == kCancelled) {
-                queue.pop_front();
-                continue;
-            }
-            const bool needs_ws = sg_sa_workspace_bytes(q.r.inst.L, 1) > 0;
-            if (active >= cfg.max_active || mem_in_use + q.footprint > cfg.memory_budget ||
-                (needs_ws && ws_free.empty()))
-                break;
+        AdmitCapacity cap{active, cfg.max_active, mem_in_use, cfg.memory_budget, static_cast<int64_t>(ws_free.size())};
+        const double now = steady_now();
+        const auto dropped = [&](uint64_t id) {
+            auto it = reqs.find(id);
+            return it == reqs.end() || it->second.state == kCancelled;
+        };
+        const std::vector<AdmitEntry> picked = admit_pick(queue, cap, now, skip_age, dropped);
+        for (const AdmitEntry &e : picked) {
+            Request &q = reqs.at(e.id);
             Lane *ln = lane_for(q.r.inst.L);
             if (!ln) {
                 q.state = kFailed;
-                q.t_done = steady_now();
-                queue.pop_front();
+                q.t_done = now;
                 continue;
             }
-            if (needs_ws) {
+            if (e.needs_ws) {
                 q.ws_slot = ws_free.back();
                 ws_free.pop_back();
             }
             q.state = kActive;
-            q.t_admit = steady_now();
+            q.t_admit = now;
             mem_in_use += q.footprint;
             ++active;
-            ln->active.push_back(queue.front());
-            queue.pop_front();
-            any = true;
+            ln->active.push_back(e.id);
         }
-        return any;
+        return !picked.empty();
     }
 
     // (lock held) stage the next chunk of a lane; returns the job count
@@ -215,7 +214,7 @@ struct sg_server {
     {
         int n = 0;
         for (uint64_t id : ln.active) {
-            Request &q = reqs[id];
+            Request &q = reqs.at(id);
             if (q.in_flight || q.state != kActive) continue;
             if (q.cancel) {  // never launched again: retire now
                 q.state = kCancelled;
@@ -249,7 +248,7 @@ struct sg_server {
         }
         // drop retired (cancelled) requests from the lane
         auto &act = ln.active;
-        act.erase(std::remove_if(act.begin(), act.end(), [&](uint64_t id) { return reqs[id].state != kActive; }),
+        act.erase(std::remove_if(act.begin(), act.end(), [&](uint64_t id) { return reqs.at(id).state != kActive; }),
                   act.end());
         return n;
     }
@@ -295,7 +294,7 @@ struct sg_server {
                 if (rc != SG_OK) {
                     thread_error = sg_last_error();
                     for (uint64_t id : ln.chunk_ids) {
-                        Request &q = reqs[id];
+                        Request &q = reqs.at(id);
                         q.in_flight = false;
                         q.state = kFailed;
                         q.t_done = steady_now();
@@ -336,6 +335,8 @@ int sg_server_create(const sg_server_config *cfg, sg_server **out)
     if (s->cfg.chunk_attempts < 0) return fail(SG_EINVAL, "sg_server_create: chunk_attempts < 0");
     if (s->cfg.memory_budget <= 0) s->cfg.memory_budget = int64_t(8) << 30;
     if (s->cfg.large_slots < 0) return fail(SG_EINVAL, "sg_server_create: large_slots < 0");
+    if (s->cfg.skip_age_ms < 0) return fail(SG_EINVAL, "sg_server_create: skip_age_ms < 0");
+    s->skip_age = (s->cfg.skip_age_ms > 0 ? s->cfg.skip_age_ms : 50) * 1e-3;
     if (hipGetDevice(&s->device) != hipSuccess) return fail(SG_EDEVICE, "sg_server_create: no device");
     s->ws_bytes = sg_sa_workspace_bytes(SG_MAX_L, 1);
     for (int i = 0; i < s->cfg.large_slots; ++i) {
@@ -382,7 +383,7 @@ int sg_server_submit(sg_server *srv, const sg_request *req, uint64_t *id_out)
     q.footprint = static_cast<int64_t>(in.L) * in.L * in.L + 4 + (needs_ws ? static_cast<int64_t>(srv->ws_bytes) : 0);
     if (q.footprint > srv->cfg.memory_budget) return fail(SG_ERANGE, "sg_server_submit: request larger than the budget");
     srv->reqs.emplace(id, q);
-    srv->queue.push_back(id);
+    srv->queue.push_back(AdmitEntry{id, q.footprint, needs_ws, steady_now()});
     ++srv->stats.submitted;
     if (id_out) *id_out = id;
     srv->cv.notify_all();
@@ -422,6 +423,19 @@ int sg_server_cancel(sg_server *srv, uint64_t id)
         return fail(SG_EINVAL, "sg_server_cancel: request already finished");
     }
     srv->cv.notify_all();
+    return SG_OK;
+}
+
+int sg_server_release(sg_server *srv, uint64_t id)
+{
+    if (!srv) return fail(SG_EINVAL, "sg_server_release: NULL server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) return fail(SG_ENOTFOUND, "sg_server_release: unknown request");
+    const int32_t st = it->second.state;
+    if (st == kQueued || st == kActive || it->second.in_flight)
+        return fail(SG_EBUSY, "sg_server_release: request %llu has not finished", (unsigned long long)id);
+    srv->reqs.erase(it);
     return SG_OK;
 }
 

@@ -20,7 +20,7 @@ SG_REQ_QUEUED, SG_REQ_ACTIVE, SG_REQ_DONE, SG_REQ_CANCELLED, SG_REQ_FAILED = ran
 class sg_server_config(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("chunk_sweeps", ctypes.c_int32),
                 ("memory_budget", ctypes.c_int64), ("large_slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("chunk_attempts", ctypes.c_int64)]
+                ("skip_age_ms", ctypes.c_int32), ("chunk_attempts", ctypes.c_int64)]
 
 
 class sg_request(ctypes.Structure):
@@ -56,10 +56,11 @@ def _lib():
         L.sg_server_submit.argtypes = [vp, c.POINTER(sg_request), c.POINTER(c.c_uint64)]
         L.sg_server_poll.argtypes = [vp, c.c_uint64, c.POINTER(sg_request_status)]
         L.sg_server_cancel.argtypes = [vp, c.c_uint64]
+        L.sg_server_release.argtypes = [vp, c.c_uint64]
         L.sg_server_get_stats.argtypes = [vp, c.POINTER(sg_server_stats)]
         L.sg_server_wait.argtypes = [vp, c.c_double]
         L.sg_server_destroy.argtypes = [vp]
-        for fn in ("sg_server_create", "sg_server_submit", "sg_server_poll", "sg_server_cancel",
+        for fn in ("sg_server_create", "sg_server_submit", "sg_server_poll", "sg_server_cancel", "sg_server_release",
                    "sg_server_get_stats", "sg_server_wait", "sg_server_destroy"):
             getattr(L, fn).restype = c.c_int
         _ready = True
@@ -70,10 +71,10 @@ class Server:
     """A running anneal server on the current device."""
 
     def __init__(self, max_active=4096, chunk_sweeps=64, memory_budget=8 << 30, large_slots=64,
-                 chunk_attempts=0):
+                 chunk_attempts=0, skip_age_ms=0):
         cfg = sg_server_config(max_active=max_active, chunk_sweeps=chunk_sweeps,
                                memory_budget=memory_budget, large_slots=large_slots,
-                               chunk_attempts=chunk_attempts)
+                               chunk_attempts=chunk_attempts, skip_age_ms=skip_age_ms)
         h = ctypes.c_void_p()
         _check(_lib().sg_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sg_server_create")
         self.h = h
@@ -108,6 +109,11 @@ class Server:
 
     def cancel(self, rid: int) -> None:
         _check(_lib().sg_server_cancel(self.h, rid), "sg_server_cancel")
+
+    def release(self, rid: int) -> None:
+        """Forget a finished request (its buffers are no longer borrowed)."""
+        _check(_lib().sg_server_release(self.h, rid), "sg_server_release")
+        self._keep.pop(rid, None)
 
     def stats(self) -> dict:
         st = sg_server_stats()
@@ -205,6 +211,8 @@ def run_poisson(torch, rate=2000.0, duration=60.0, warmup=5.0, seed=0x5E7E, pool
     srv.wait(timeout_s=600.0)
     end = srv.now()
     st = [srv.poll(r) for r in ids]
+    for r in ids:
+        srv.release(r)
     stats = srv.stats()
     srv.close()
     arrive = np.array([s["t_arrival"] for s in st])

@@ -202,3 +202,43 @@ def test_split_argument_errors():
     small = torch.empty(4, dtype=torch.int64, device="cuda")
     with pytest.raises(sg.SgError):
         sg.pt_run(inst, thr, thrx, 2, 4, 1, groups=2, workspace=small)
+
+
+@pytest.mark.parametrize("groups", [1, 2])
+def test_pos_that_is_not_a_permutation_falls_back_to_identity(groups):
+    # a caller's pos with a repeated slot (bypassing the binding's check,
+    # straight through the C ABI): the run starts from the identity order
+    # instead, so it equals a run given the identity, and the split form's
+    # status word carries bit 1
+    import ctypes
+    L, T, n_runs, n_steps, seed = 8, 8, 2, 9, 0xB0B
+    log(f"PT bad pos groups={groups}")
+    inst, Jo, go, egs = instance(L, 0xB0B0 + groups, 0)
+    thr, thrx = _ladder(T)
+    dthr, dthrx = dev_u32(thr), dev_u32(thrx)
+    start = sg.pt_run(inst, dthr, dthrx, n_runs, 3, seed)
+    sp0 = start["spins"].clone()
+    ident = torch.arange(T, dtype=torch.int32, device="cuda").repeat(n_runs, 1).contiguous()
+    ref = sg.pt_run(inst, dthr, dthrx, n_runs, n_steps, seed, step0=3, spins=sp0.clone(), pos=ident.clone(),
+                    want_trace=True, groups=groups)
+    bad = ident.clone()
+    bad[0, 3] = 5                         # slot 5 twice, slot 3 empty
+    bad[1, 0] = T + 4                     # out of range
+    sp = sp0.clone()
+    en = torch.empty((n_runs, T), dtype=torch.int32, device="cuda")
+    tr = torch.empty((n_runs, n_steps), dtype=torch.int32, device="cuda")
+    args = sg.sg_pt_args(n_runs=n_runs, run0=0, T=T, n_steps=n_steps, step0=3, K=int(dthr.shape[1]),
+                         M=int(dthrx.shape[1]), init_random=0, seed=seed)
+    nb = sg.pt_split_workspace_bytes(n_runs, T)
+    ws = torch.empty((nb + 7) // 8, dtype=torch.int64, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = sg.lib().sg_pt_run_split(ctypes.byref(inst.struct()), ctypes.byref(args), groups, 0, p(dthr), p(dthrx),
+                                  p(sp), p(en), p(bad), p(tr), None, p(ws), nb,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(ws.view(torch.int32)[0].item()) == 2
+    assert torch.equal(sp, ref["spins"]) and torch.equal(en, ref["energy"])
+    assert torch.equal(bad, ref["pos"]) and torch.equal(tr, ref["emin_trace"])
+    with pytest.raises(sg.SgError):
+        sg.pt_run(inst, dthr, dthrx, n_runs, 2, seed, spins=sp0.clone(), pos=ident.flip(1).contiguous() * 0)
