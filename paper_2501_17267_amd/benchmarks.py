@@ -304,6 +304,40 @@ def wide(a, sg, wl, torch):
     return out
 
 
+def large(a, sg, wl, torch):
+    """The large-lattice path at a replica count that fills the device: 256
+    replicas of one instance at L = 32 (spins in LDS, couplings streamed from
+    the encoded image) and at L = 64 (spins in the workspace too), 256 sweeps,
+    one work group per replica group; and one replica of each on the wide
+    path (one launch per colour phase).  Roofline: the 20-slot VALU model
+    against 39.3 T lane-ops/s, and HBM against 8 TB/s at 2 B per attempt (a
+    spin read and written once per sweep when nothing stays cached)."""
+    out = {"metric": "spin-flip attempts/s of the large-lattice kernels (256 replicas x 256 sweeps)", "rows": []}
+    S, R = 256, 256
+    thr = sg.to_device_u32(sg.make_thresholds(sg.make_schedule(0, 0.1, 3.0, S)))
+    stream = torch.cuda.current_stream()
+    for L in (32, 64):
+        inst = sg.Instance.generate(L, wl.instance_seed("sa_batch", 64000 + L), chain=1)
+        v = sg.selected_variant(L)
+        res = {}
+
+        def fn():
+            res["out"] = sg.sa_anneal_variant(inst, thr, R, 5, v)
+        ms = _time(torch, fn, a.steps, a.warmup, stream)
+        att = R * S * L ** 3
+        rate = att / (ms * 1e-3)
+        one = {}
+
+        def fn1():
+            one["out"] = sg.sa_anneal(inst, thr, 1, 5)
+        ms1 = _time(torch, fn1, max(2, a.steps // 2), 1, stream)
+        out["rows"].append({"L": L, "replicas": R, "sweeps": S, "variant": v, "ms": ms, "attempts_per_s": rate,
+                            "valu_frac_20_slot": 20 * rate / VALU32_PEAK,
+                            "hbm_frac_2B": 2 * rate / 8e12,
+                            "one_replica_wide_ms": ms1, "one_replica_us_per_sweep": ms1 * 1e3 / S})
+    return out
+
+
 def pticm(a, sg, wl, torch):
     """PT with isoenergetic cluster moves at the tuned ladder (L = 12, T = 4
     slots x 2 copies, beta 0.2 -> 2.0, moves on every slot), 128 runs x 200
@@ -360,5 +394,5 @@ def pt_tteps(a, sg, wl, torch):
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
           "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "fragment_call": fragment_call, "tn": tn, "tuning": tuning, "pt_tteps": pt_tteps,
-          "wide": wide, "pticm": pticm}[name]
+          "wide": wide, "pticm": pticm, "large": large}[name]
     return fn(a, sg, wl, torch)
