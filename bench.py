@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "fragment_call", "tn", "tuning", "pt_tteps", "wide", "pticm", "large", "microbench",
+    ap.add_argument("--workload", default="uneven", choices=["sa_batch", "sa_small", "plain", "pt", "uneven", "serve", "tteps", "fragment", "fragment_call", "tn", "tuning", "pt_tteps", "wide", "pticm", "large", "tn_call", "microbench",
                              "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pt-groups", type=int, default=0,

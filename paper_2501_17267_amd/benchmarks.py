@@ -338,6 +338,30 @@ def large(a, sg, wl, torch):
     return out
 
 
+def tn_call(a, sg, wl, torch):
+    """One 20-instance decimation of the tensor-network optimiser's measured
+    setting (L = 20, l = 5, beta = 2, wavefront order): ms per call and the
+    workspace-tier step's algorithmic bytes per call (8 B per canonical read
+    and per written entry), the unit its roofline is taken on."""
+    from . import tn_study
+    L, n = 20, 20
+    plan = sg.TnPlan(L, 2, 1)
+    J, egs = tn_study._batch(torch, L, n)
+    ws = torch.empty((plan.workspace_bytes(n, True) + 7) // 8, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def fn():
+        res["out"] = sg.tn_decimate(plan, J, 2.0, workspace=ws, want_score=False)
+    ms = _time(torch, fn, a.steps, a.warmup, stream)
+    eps = tn_study._eps(res["out"][1], egs)
+    plan.close()
+    step_bytes = tn_study.workspace_step_bytes(L, 2, n, 8)
+    return {"metric": "ms per 20-instance tensor-network decimation (L = 20, l = 5, beta = 2)", "ms_per_call": ms,
+            "ms_per_instance": ms / n, "workspace_step_bytes_per_call": step_bytes,
+            "step_bytes_per_s_over_whole_call": step_bytes / (ms * 1e-3), "eps_mean": float(eps.mean())}
+
+
 def pticm(a, sg, wl, torch):
     """PT with isoenergetic cluster moves at the tuned ladder (L = 12, T = 4
     slots x 2 copies, beta 0.2 -> 2.0, moves on every slot), 128 runs x 200
@@ -394,5 +418,5 @@ def pt_tteps(a, sg, wl, torch):
 def run(name, a, sg, wl, torch):
     fn = {"microbench": microbench, "copy": copy, "sa_small": sa_small, "plain": plain, "pt": pt,
           "uneven": uneven, "serve": serve, "tteps": tteps, "fragment": fragment, "fragment_call": fragment_call, "tn": tn, "tuning": tuning, "pt_tteps": pt_tteps,
-          "wide": wide, "pticm": pticm, "large": large}[name]
+          "wide": wide, "pticm": pticm, "large": large, "tn_call": tn_call}[name]
     return fn(a, sg, wl, torch)

@@ -36,9 +36,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _stale(src: str, newest_header: float) -> bool:
+def _deps(path: str, seen: set) -> set:
+    """The file and the project headers it includes, transitively."""
+    import re
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for name in re.findall(r'^\s*#include\s+"([^"]+)"', open(path).read(), re.M):
+        for d in (CSRC, os.path.join(ROOT, "include")):
+            if os.path.exists(os.path.join(d, name)):
+                _deps(os.path.join(d, name), seen)
+                break
+    return seen
+
+
+def _stale(src: str) -> bool:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    return not os.path.exists(obj) or os.path.getmtime(obj) < max(os.path.getmtime(src), newest_header)
+    if not os.path.exists(obj):
+        return True
+    return os.path.getmtime(obj) < max(os.path.getmtime(f) for f in _deps(src, set()))
 
 
 def build(jobs: int | None = None, incremental: bool = False) -> str:
@@ -47,10 +63,7 @@ def build(jobs: int | None = None, incremental: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     if incremental:
-        hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-        hdrs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
-        newest = max(os.path.getmtime(h) for h in hdrs)
-        todo = [s for s in srcs if _stale(s, newest)]
+        todo = [s for s in srcs if _stale(s)]
     else:
         todo = srcs
     jobs = jobs or min(8, len(srcs))
