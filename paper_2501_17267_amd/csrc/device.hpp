@@ -197,10 +197,10 @@ __device__ __forceinline__ uint32_t kb_addr(uint32_t kb)
     return __builtin_amdgcn_ubfe(kb, 8 * B - 2, 10);
 }
 
-// byte sum of a dword
+// byte sum of a dword (an unsigned byte dot product with 1, 1, 1, 1)
 __device__ __forceinline__ uint32_t byte_sum(uint32_t v)
 {
-    return (v & 0xFFu) + ((v >> 8) & 0xFFu) + ((v >> 16) & 0xFFu) + (v >> 24);
+    return __builtin_amdgcn_udot4(v, 0x01010101u, 0u, false);
 }
 
 }  // namespace sg

@@ -186,7 +186,7 @@ int sg_sa_anneal_wide(const sg_instance *inst, const sg_sa_args *args, const uin
     const int rc = check_sa_args("sg_sa_anneal_wide", inst, args, thr, spins, energy);
     if (rc != SG_OK) return rc;
     if (!wide_supported(inst->L))
-        return fail(SG_EUNSUPPORTED, "sg_sa_anneal_wide: L = %d (the wide path covers L = 26..32 and 64)", inst->L);
+        return fail(SG_EUNSUPPORTED, "sg_sa_anneal_wide: L = %d (the wide path covers even L = 26..64)", inst->L);
     const size_t need = wide_bytes(inst->L, args->n_rep);
     if (!args->workspace || args->workspace_bytes < static_cast<int64_t>(need))
         return fail(SG_EINVAL, "sg_sa_anneal_wide: needs a %zu-byte workspace", need);

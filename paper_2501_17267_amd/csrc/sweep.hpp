@@ -272,7 +272,15 @@ struct Column {
             // downhill (k <= 0, i.e. 4 Kb <= 128) always; uphill iff u < thr[k]
             const bool acc = (addr[b] <= 4u * kKbBias) | (u.w[b] < t);
             flip |= acc ? (0xFFu << (8 * b)) : 0u;
-            if (TRACK) dE += acc ? 2 * (static_cast<int32_t>(addr[b] >> 2) - static_cast<int32_t>(kKbBias)) : 0;
+        }
+        if (TRACK) {
+            // an accepted flip changes the energy by 2 (Kb - 32).  Read as
+            // int8, an accepted byte of `flip` is -1 and a Kb byte (below
+            // 64) is itself, so two byte dot products give minus the sum of
+            // Kb - 32 over the accepted sites (0xE0 is -32)
+            int32_t nh = __builtin_amdgcn_sdot4(static_cast<int32_t>(flip), static_cast<int32_t>(kbm), 0, false);
+            nh = __builtin_amdgcn_sdot4(static_cast<int32_t>(flip), static_cast<int32_t>(0xE0E0E0E0u), nh, false);
+            dE -= 2 * nh;
         }
         return flip;
     }
