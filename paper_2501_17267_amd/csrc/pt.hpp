@@ -345,17 +345,33 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
                 __syncthreads();
             }
         }
+        // Wave 0 (T <= 64 walkers, lane w holds walker w) runs the exchange
+        // of ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ..., lane k
+        // deciding pair k.  Its random word follows from the counter alone,
+        // so it is drawn before the energies are complete; the energies go
+        // from lane to lane in registers.  Meanwhile the other waves draw
+        // their colour-0 words of the next step.
+        const int w = tid;
+        const bool pair = w + 1 < T && ((w ^ static_cast<int>(t)) & 1) == 0;
+        int32_t e = 0;
+        uint32_t ux = 0;
+        int a = 0, b = 0;
+        if (tid < 64) {
+            if (pair) {
+                ux = philox10(static_cast<uint32_t>(w), t, 0xFFFFFFFFu, chain, k0, k1).w[0];
+                a = s_who[w];
+                b = s_who[w + 1];
+            }
+            if (w < T) e = s_E[w];
+        }
         if constexpr (SPLIT) {
-            // wave 0: publish this group's energies, collect the others',
-            // then exchange; T <= 64 walkers, one lane each.  Between the
-            // publishing and the wait every wave draws its colour-0 words of
-            // the next step.
-            const int w = tid;
+            // publish this group's energies, draw, then collect the other
+            // groups' (every wave draws between the publishing and the wait)
             uint64_t *box = job.mbox + (static_cast<int64_t>(run) * 2 + (ti & 1)) * T;
             const uint32_t tag = static_cast<uint32_t>(ti) + 1u;
             const bool mine = w >= w0 && w < w0 + TG;
             if (tid < 64 && mine)
-                __hip_atomic_store(box + w, (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(s_E[w]),
+                __hip_atomic_store(box + w, (static_cast<uint64_t>(tag) << 32) | static_cast<uint32_t>(e),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (NPRE > 0 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
             if (tid < 64) {
@@ -371,51 +387,43 @@ void k_pt(PtJob job, uint32_t k0, uint32_t k1)
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    s_E[w] = static_cast<int32_t>(static_cast<uint32_t>(v));
+                    e = static_cast<int32_t>(static_cast<uint32_t>(v));
+                    s_E[w] = e;
                 }
                 if (__any(gave_up)) {
                     if (!dead && w == 0) atomicOr(job.status, 1);
                     dead = true;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
             }
-        }
-        // one group per run: the waves other than wave 0 draw the next
-        // step's colour-0 words while wave 0 runs the exchange
-        if constexpr (!SPLIT)
+        } else {
             if (NPRE > 0 && tid >= 64 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
-        // exchange of ladder pairs (k, k+1), k = t mod 2, t mod 2 + 2, ...
-        const int k = tid;
-        if (k + 1 < T && ((k ^ static_cast<int>(t)) & 1) == 0) {
-            const int a = s_who[k], b = s_who[k + 1];
-            const int32_t D = s_E[a] - s_E[b];
-            bool acc = D <= 0;
-            if (!acc) {
-                const int32_t m = D / 2;
-                const Rand4 u = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFFu, chain, k0, k1);
-                if (m <= mx)
-                    acc = u.w[0] < s_thrx[k * mx + (m - 1)];
-                else
-                    acc = (m <= job.M) && (u.w[0] < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
-            }
-            if (acc) {
-                s_who[k] = b;
-                s_who[k + 1] = a;
-                s_pos[b] = k;
-                s_pos[a] = k + 1;
-                s_sw[k] += 1;
-            }
         }
-        // minimum energy of the step: another wave when the energies are
-        // all local, wave 0 (which collected them) in the split form
-        constexpr int kTraceLo = SPLIT ? 0 : 64;
-        if (job.emin_trace && g == 0 && tid >= kTraceLo && tid < kTraceLo + 64) {
-            const int lane = tid - kTraceLo;
-            int32_t e = 0x7FFFFFFF;
-            for (int w = lane; w < T; w += 64) e = min(e, s_E[w]);
-            for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
-            if (lane == 0) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = e;
+        if (tid < 64) {
+            const int32_t ea = __shfl(e, a, 64), eb = __shfl(e, b, 64);
+            if (pair) {
+                const int32_t D = ea - eb;
+                bool acc = D <= 0;
+                if (!acc) {
+                    const int32_t m = D / 2;
+                    if (m <= mx)
+                        acc = ux < s_thrx[w * mx + (m - 1)];
+                    else
+                        acc = (m <= job.M) && (ux < job.thrx[static_cast<int64_t>(w) * job.M + (m - 1)]);
+                }
+                if (acc) {
+                    s_who[w] = b;
+                    s_who[w + 1] = a;
+                    s_pos[b] = w;
+                    s_pos[a] = w + 1;
+                    s_sw[w] += 1;
+                }
+            }
+            // minimum energy of the step (group 0 of a split run)
+            if (job.emin_trace && g == 0) {
+                int32_t mn = w < T ? e : 0x7FFFFFFF;
+                for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off, 64));
+                if (w == 0) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = mn;
+            }
         }
         if constexpr (!SPLIT)
             if (NPRE > 0 && tid < 64 && ti + 1 < job.n_steps) draw_colour0(t + 1u);
