@@ -3,15 +3,16 @@
 // PT by Zhu, Ochoa and Katzgraber) and its C-ABI entry point.
 //
 // One work group runs one run: two copies of a T-slot ladder (2T walkers),
-// all LDS-resident in the colour-split column layout.  A step is the sweep
-// of every walker, then for every slot k >= icm_from one cluster move
-// between the two walkers at slot k, then the even/odd exchanges inside
-// each copy.  A cluster move works on byte masks in the same layout as the
-// spins: the disagreement mask is the XOR of the two walkers, a block-wide
-// prefix count picks the seed, and the cluster grows by repeated expansion
-// through neighbouring disagreeing sites joined by nonzero couplings (the
-// same byte shuffles as the local fields) until a pass adds nothing; both
-// walkers then XOR the cluster in.
+// all LDS-resident in the colour column layout.  A step is the sweep of
+// every walker, then for every slot k >= icm_from one cluster move between
+// the two walkers at slot k, then the even/odd exchanges inside each copy.
+// The moves of different slots touch different walkers, so each slot's move
+// is run by one wave on its own, with no block barrier: the disagreement
+// of the two walkers and the cluster are held as bits (one dword per double
+// column, see IcmBits), a wave prefix count over (colour, column, height)
+// picks the seed, the cluster grows breadth first (every site of the
+// frontier at once, one hop per round) until a round adds nothing, and
+// both walkers then flip it.
 #include <algorithm>
 
 #include "common.hpp"
@@ -33,107 +34,230 @@ struct PtIcmJob {
     int32_t *icm_flipped;   // [n_runs][n_steps] or NULL
     uint32_t run0;
     int32_t T, n_steps, step0, K, M, icm_from, init_random;
-    int32_t G;              // slots whose cluster moves run together
 };
 
 constexpr int kIcmNW = 12;          // 768 lanes per run
 constexpr int kIcmThr = kThrEntries;
 
-// LDS of one run with cluster moves of ng slots at once
+// One slot's sites as bits.  Item col is the double column of index col:
+// both colour columns, i.e. the sites with x in {2k, 2k+1} at one y, every
+// z.  Its dword holds the colour-0 sites at bits z = 0..L-1 and the
+// colour-1 sites at bits L + z.  Every bond joins the two colours, so the
+// neighbours of a site are bits of the other half: z +- 1 and the x link
+// inside the item in the same dword; the other x link (to item k-1 for even
+// x, k+1 for odd x) and the y links in the neighbouring items' dwords.
+template <int L>
+struct IcmBits {
+    static_assert(L <= 16, "a double column must fit a dword");
+    static constexpr int NC = Geo<L>::NC;
+    static constexpr int NI = (NC + 63) / 64;   // items per lane
+    static constexpr int ROW = 64 * NI;         // a wave's cluster row: one dword per lane and item
+    static constexpr uint32_t FULL = L == 16 ? 0xFFFFFFFFu : (1u << (2 * L)) - 1u;
+    static constexpr uint32_t LOW = 1u | (1u << L);                       // z = 0 of each half
+    static constexpr uint32_t HIGH = (1u << (L - 1)) | (1u << (2 * L - 1));  // z = L-1 of each half
+    // the two halves exchanged
+    __device__ static uint32_t swap(uint32_t v) { return ((v >> L) | (v << L)) & FULL; }
+    // bit z of each half to z + 1, periodic in L
+    __device__ static uint32_t up(uint32_t v) { return ((v << 1) & ~LOW & FULL) | ((v >> (L - 1)) & LOW); }
+    // bit z of each half to z - 1, periodic in L
+    __device__ static uint32_t down(uint32_t v) { return ((v >> 1) & ~HIGH) | ((v << (L - 1)) & HIGH); }
+    // the four 0x00/0xFF bytes of a column dword as four bits
+    __device__ static uint32_t gather4(uint32_t v) { return ((v & 0x01010101u) * 0x01020408u) >> 24; }
+    // four bits as 0x00/0xFF bytes
+    __device__ static uint32_t spread4(uint32_t b)
+    {
+        const uint32_t t = (b * 0x00204081u) & 0x01010101u;   // b < 16: a 24-bit product
+        return (t << 8) - t;
+    }
+    // bits of column dword m inside a half (the tail dword has fewer heights)
+    static constexpr uint32_t dword_bits(int m) { return L - 4 * m >= 4 ? 0xFu : (1u << (L - 4 * m)) - 1u; }
+};
+
+// LDS of one run: walkers, couplings, thresholds, ladder words, the
+// nonzero-coupling masks (bytes, then bits) and one cluster row per wave
 template <int L, bool JF>
-constexpr size_t pticm_lds_bytes(int T, int ng)
+constexpr size_t pticm_lds_bytes(int T)
 {
     using G = Geo<L>;
     const size_t W = 2 * static_cast<size_t>(T);
     return (W * G::SPIN_DW + G::jdw_odd(JF ? 2 : 1) + static_cast<size_t>(T) * kIcmThr + 3 * W +
-            2 * (static_cast<size_t>(T) - 1) + 2 * static_cast<size_t>(ng) * G::SPIN_DW + 64 +
-            2 * static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW)) * 4;
+            2 * (static_cast<size_t>(T) - 1) + static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW) +
+            7 * static_cast<size_t>(G::NC) + static_cast<size_t>(kIcmNW) * IcmBits<L>::ROW) * 4;
 }
 
-// One growth pass over the double column `col` of one slot's cluster: both
-// colour columns of index col, i.e. the sites with x in {2k, 2k+1} at one
-// y, every z.  Its z-links and half of its x-links stay inside it.  The
-// pass reads the cluster bits of the four neighbouring double columns
-// once, then adds, until nothing changes, every disagreeing site (q) joined
-// by a nonzero coupling (nz: [6][SPIN_DW] masks) to a cluster site, inside
-// the item or in those neighbours.  cl is the cluster, laid out like q.
-// Returns 1 if anything was added.  Bits other lanes add meanwhile are seen
-// by a later pass, so the fixpoint of the passes is the connected component
-// of the seed, whatever the order.
+// Directions of the link masks (receiving site's coupling nonzero), kept
+// with the halves exchanged so that they apply to the sending side's bits:
+// +z, -z, the x link inside the item, -x to item k-1, +x to item k+1, +y, -y
+enum : int { kLmZp = 0, kLmZm, kLmXin, kLmXm, kLmXp, kLmYp, kLmYm, kLmN };
+
+// exclusive prefix sum over the lanes of a wave, and the wave total
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
+{
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// position of the j-th set bit (j counted from 0) of f
+__device__ __forceinline__ uint32_t nth_bit(uint32_t f, int j)
+{
+    for (int z = 0; z < 32; ++z)
+        if ((f >> z) & 1u) {
+            if (j == 0) return 1u << z;
+            --j;
+        }
+    return 0u;
+}
+
+// The cluster move of one slot between walkers wa and wb (two copies at the
+// same ladder slot k), run by one whole wave.  lm: link masks [kLmN][NC];
+// wcl: the wave's cluster row [IcmBits::ROW].  The lanes read each other's
+// items through wcl, so the growth loop keeps the whole wave together: no
+// lane branches inside it, every lane stores all its slots every round.  Writes the two walkers' new energies
+// and the cluster size (0 when the walkers agree everywhere).
 template <int L, bool JF>
-__device__ int icm_grow_column(const uint32_t *q, uint32_t *cl, const uint32_t *nz, int col)
+__device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint32_t *lm, uint32_t *wcl, int wa,
+                              int wb, int k, uint32_t t, uint32_t chain, uint32_t k0, uint32_t k1, int lane,
+                              int32_t *s_E, int32_t *size_out)
 {
     using G = Geo<L>;
+    using B = IcmBits<L>;
     using Col = Column<L, JF, kColMajor, kColMajorOdd>;
-    constexpr int C = G::C, NC = G::NC, SDW = G::SPIN_DW;
-    uint32_t qq[2][C], cc[2][C];
-    uint32_t open = 0;
+    constexpr int NC = G::NC, C = G::C, SDW = G::SPIN_DW, NI = B::NI;
+    uint32_t *sa = s_spin + wa * SDW;
+    uint32_t *sb = s_spin + wb * SDW;
+    // 1. the disagreeing sites as bits
+    uint32_t q[NI], cl[NI];
+    int n0[NI], n1[NI];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int i = 0; i < NI; ++i) {
+        const int I = lane + 64 * i;
+        q[i] = 0u;
+        if (I < NC) {
 #pragma unroll
-        for (int m = 0; m < C; ++m) {
-            qq[c][m] = q[(c * NC + col) * C + m];
-            cc[c][m] = cl[(c * NC + col) * C + m];
-            open |= qq[c][m] & ~cc[c][m];
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int m = 0; m < C; ++m) {
+                    const int w = (c * NC + I) * C + m;
+                    q[i] |= (B::gather4(sa[w] ^ sb[w]) & B::dword_bits(m)) << (c * L + 4 * m);
+                }
         }
-    if (!open) return 0;   // every disagreeing site here is in already
-    const typename Col::Nbr n = Col::neighbours(0, col);
-    // first what the neighbouring double columns reach (added at once);
-    // ix, nzp, nzm: the nonzero-coupling masks of the links inside the item
-    // (x, +z, -z)
-    uint32_t ix[2][C], nzp[2][C], nzm[2][C];
-    uint32_t first = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t ex = c ? ~n.even_x : n.even_x;   // bytes whose x is even
-        const int oc = c ^ 1;
-#pragma unroll
-        for (int m = 0; m < C; ++m) {
-            const int w = (c * NC + col) * C + m;
-            const uint32_t xp = cl[(oc * NC + n.xp) * C + m], xm = cl[(oc * NC + n.xm) * C + m];
-            const uint32_t yp = cl[(oc * NC + n.yp) * C + m], ym = cl[(oc * NC + n.ym) * C + m];
-            const uint32_t z0 = nz[w], z1 = nz[SDW + w];
-            const uint32_t nw = ((xp & ~ex & z0) | (xm & ex & z1) | (yp & nz[2 * SDW + w]) | (ym & nz[3 * SDW + w])) &
-                                qq[c][m] & ~cc[c][m];
-            cc[c][m] |= nw;
-            first |= nw;
-            ix[c][m] = (z0 & ex) | (z1 & ~ex);
-            nzp[c][m] = nz[4 * SDW + w];
-            nzm[c][m] = nz[5 * SDW + w];
-        }
+        n0[i] = __popc(q[i] & ((1u << L) - 1u));
+        n1[i] = __popc(q[i] >> L);
     }
-    int added = first != 0;
-    for (;;) {   // ends: every round adds a site or stops
-        uint32_t ch = 0;
+    // 2. the seed: the r-th disagreeing site in the order (colour, column,
+    // height), r drawn from the slot's counter
+    int p0[NI], p1[NI], tot = 0, N0 = 0;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const uint32_t(&S)[C] = cc[c ^ 1];
-#pragma unroll
-            for (int m = 0; m < C; ++m) {
-                uint32_t zp, zm;
-                if (G::TAIL != 0 && m == C - 1)
-                    zp = __builtin_amdgcn_perm(S[0], S[C - 1], 0x00000401u);
-                else
-                    zp = __builtin_amdgcn_alignbyte(S[(m + 1) % C], S[m], 1);
-                if (G::TAIL != 0 && m == 0)
-                    zm = __builtin_amdgcn_perm(S[0], S[C - 1], 0x06050401u);
-                else
-                    zm = __builtin_amdgcn_alignbyte(S[m], S[(m + C - 1) % C], 3);
-                const uint32_t reach = (S[m] & ix[c][m]) | (zp & nzp[c][m]) | (zm & nzm[c][m]);
-                const uint32_t nw = reach & qq[c][m] & ~cc[c][m];
-                cc[c][m] |= nw;
-                ch |= nw;
-            }
-        }
-        if (!ch) break;
-        added = 1;
+    for (int i = 0; i < NI; ++i) {
+        p0[i] = N0 + wave_excl_scan(n0[i], lane, tot);
+        N0 += tot;
     }
-    if (added)
+    int N1 = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        p1[i] = N0 + N1 + wave_excl_scan(n1[i], lane, tot);
+        N1 += tot;
+    }
+    const int n = N0 + N1;
+    if (n == 0) {
+        if (lane == 0) *size_out = 0;
+        return;
+    }
+    const Rand4 uu = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFEu, chain, k0, k1);
+    const int r = static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        cl[i] = 0u;
+        if (r >= p0[i] && r < p0[i] + n0[i]) cl[i] = nth_bit(q[i] & ((1u << L) - 1u), r - p0[i]);
+        if (r >= p1[i] && r < p1[i] + n1[i]) cl[i] = nth_bit(q[i] >> L, r - p1[i]) << L;
+    }
+    // 3. growth: a round gives every disagreeing site linked to the cluster
+    // to it; the rounds end at the connected component of the seed
+    uint32_t msk[NI][kLmN];
+    int nxm[NI], nxp[NI], nyp[NI], nym[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int I = lane + 64 * i;
+        const int Ia = I < NC ? I : 0;
+#pragma unroll
+        for (int d = 0; d < kLmN; ++d) msk[i][d] = I < NC ? lm[d * NC + Ia] : 0u;
+        const typename Col::Nbr nb = Col::neighbours(0, Ia);
+        nxm[i] = nb.xm;
+        nxp[i] = nb.xp;
+        nyp[i] = nb.yp;
+        nym[i] = nb.ym;
+        wcl[I] = cl[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (;;) {
+        uint32_t grown = 0;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const uint32_t a = wcl[nxm[i]], b = wcl[nxp[i]], c = wcl[nyp[i]], d = wcl[nym[i]];
+            const uint32_t own = cl[i];
+            uint32_t A = (B::down(own) & msk[i][kLmZp]) | (B::up(own) & msk[i][kLmZm]) | (own & msk[i][kLmXin]);
+            A |= (a & msk[i][kLmXm]) | (b & msk[i][kLmXp]) | (c & msk[i][kLmYp]) | (d & msk[i][kLmYm]);
+            const uint32_t nw = B::swap(A) & q[i] & ~own;
+            cl[i] = own | nw;
+            grown |= nw;
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) wcl[lane + 64 * i] = cl[i];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (!__any(grown != 0u)) break;
+    }
+    // 4. both walkers flip the cluster
+    int size = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int I = lane + 64 * i;
+        if (I >= NC || !cl[i]) continue;
+        size += __popc(cl[i]);
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int m = 0; m < C; ++m) cl[(c * NC + col) * C + m] = cc[c][m];
-    return added;
+            for (int m = 0; m < C; ++m) {
+                const uint32_t bits = (cl[i] >> (c * L + 4 * m)) & B::dword_bits(m);
+                if (!bits) continue;
+                const uint32_t f = B::spread4(bits);
+                const int w = (c * NC + I) * C + m;
+                sa[w] ^= f;
+                sb[w] ^= f;
+            }
+    }
+    size = wave_sum(size);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // 5. the two walkers' energies (Eq. 1) from their new spins
+    int ea = 0, eb = 0;
+    for (int u = lane; u < 2 * NC; u += 64) {
+        if (u < NC)
+            ea += Col::column_energy_of(sa, s_j, u);
+        else
+            eb += Col::column_energy_of(sb, s_j, u - NC);
+    }
+    ea = wave_sum(ea);
+    eb = wave_sum(eb);
+    if (lane == 0) {
+        s_E[wa] = ea;
+        s_E[wb] = eb;
+        *size_out = size;
+    }
 }
 
 template <int L, bool JF>
@@ -153,12 +277,10 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     int32_t *s_pos = s_E + W;
     int32_t *s_who = s_pos + W;                              // [copy * T + slot]
     int32_t *s_sw = s_who + W;                               // [copy * (T-1) + k]
-    uint32_t *s_q = reinterpret_cast<uint32_t *>(s_sw + 2 * (T - 1));   // disagreement masks [G][SDW]
-    uint32_t *s_cl = s_q + job.G * SDW;                      // cluster masks [G][SDW]
-    int32_t *s_misc = reinterpret_cast<int32_t *>(s_cl + job.G * SDW);   // 64 words: scan, flip counts
-    int32_t *s_n = s_misc + 64;                              // [G] disagreeing sites per slot
-    int32_t *s_tgt = s_n + T;                                // [G] seed position per slot
-    uint32_t *s_nz = reinterpret_cast<uint32_t *>(s_tgt + T);  // [6][SDW] nonzero-coupling masks
+    int32_t *s_fl = s_sw + 2 * (T - 1);                      // [T] cluster size per slot, this step
+    uint32_t *s_nz = reinterpret_cast<uint32_t *>(s_fl + T);  // [6][SDW] nonzero-coupling masks
+    uint32_t *s_lm = s_nz + 6 * SDW;                         // [kLmN][NC] link masks as bits
+    uint32_t *s_wcl = s_lm + kLmN * G::NC;                   // [kIcmNW][ROW] cluster rows
 
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = tid & 63, wave = tid >> 6;
@@ -197,6 +319,35 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
 #pragma unroll
         for (int d = 0; d < 6; ++d) s_nz[d * SDW + w] = Col::nonzero_coupling(s_j, c, col, d, m);
     }
+    if (tid < T) s_fl[tid] = 0;
+    __syncthreads();
+    // the same links as bits, per item (double column) and direction, in the
+    // receiving site's frame, stored with the halves exchanged
+    for (int it = tid; it < G::NC; it += NT) {
+        using B = IcmBits<L>;
+        const uint32_t even0 = Col::neighbours(0, it).even_x;   // colour-0 bytes whose x is even
+        uint32_t lmk[kLmN] = {};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t ex = c ? ~even0 : even0;
+#pragma unroll
+            for (int m = 0; m < G::C; ++m) {
+                const int w = (c * G::NC + it) * G::C + m;
+                const int sh = c * L + 4 * m;
+                const uint32_t keep = B::dword_bits(m);
+                const uint32_t z0 = s_nz[w], z1 = s_nz[SDW + w];
+                lmk[kLmZp] |= (B::gather4(s_nz[4 * SDW + w]) & keep) << sh;
+                lmk[kLmZm] |= (B::gather4(s_nz[5 * SDW + w]) & keep) << sh;
+                lmk[kLmXin] |= (B::gather4((z0 & ex) | (z1 & ~ex)) & keep) << sh;
+                lmk[kLmXm] |= (B::gather4(z1 & ex) & keep) << sh;
+                lmk[kLmXp] |= (B::gather4(z0 & ~ex) & keep) << sh;
+                lmk[kLmYp] |= (B::gather4(s_nz[2 * SDW + w]) & keep) << sh;
+                lmk[kLmYm] |= (B::gather4(s_nz[3 * SDW + w]) & keep) << sh;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < kLmN; ++d) s_lm[d * G::NC + it] = B::swap(lmk[d]);
+    }
     {
         uint8_t *sb = reinterpret_cast<uint8_t *>(s_spin);
         constexpr int Q = G::N / 4;
@@ -228,124 +379,11 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
             }
             __syncthreads();
         }
-        // ---- 2. cluster moves: the slots icm_from.. in groups of G at once -------
-        // (the slots' walker pairs are disjoint, so the moves are independent).
-        // Element p = g * SDW + w is dword w of slot k0s + g; each lane owns a
-        // contiguous range of elements, so a block scan over the lanes orders
-        // the disagreeing sites slot by slot, then by (colour, column, height).
-        int32_t flipped = 0;
-        for (int k0s = job.icm_from; k0s < T; k0s += job.G) {
-            const int gn = min(job.G, T - k0s);
-            const int tot = gn * SDW;
-            const int per = (tot + NT - 1) / NT;
-            const int p0 = min(tid * per, tot), p1 = min(p0 + per, tot);
-            if (tid < gn) s_n[tid] = 0;
-            __syncthreads();
-            int lsum = 0;
-            for (int p = p0; p < p1; ++p) {
-                const int g = p / SDW, w = p - g * SDW;
-                const uint32_t q = s_spin[s_who[k0s + g] * SDW + w] ^ s_spin[s_who[T + k0s + g] * SDW + w];
-                s_q[p] = q;
-                s_cl[p] = 0u;
-                const int cnt = __popc(q) >> 3;
-                if (cnt) atomicAdd(&s_n[g], cnt);
-                lsum += cnt;
-            }
-            int incl = lsum;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += v;
-            }
-            if (lane == 63) s_misc[wave] = incl;
-            __syncthreads();
-            if (tid == 0) {
-                int acc = 0;
-                for (int w = 0; w < kIcmNW; ++w) {
-                    const int v = s_misc[w];
-                    s_misc[w] = acc;
-                    acc += v;
-                }
-            }
-            if (tid < gn) {
-                // seed of slot k0s + tid: its position among all disagreeing
-                // sites of the group (-1: the two walkers agree everywhere)
-                int start = 0;
-                for (int g = 0; g < tid; ++g) start += s_n[g];
-                const int n = s_n[tid];
-                int tgt = -1;
-                if (n > 0) {
-                    const Rand4 uu = philox10(static_cast<uint32_t>(k0s + tid), t, 0xFFFFFFFEu, chain, k0, k1);
-                    tgt = start + static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
-                }
-                s_tgt[tid] = tgt;
-            }
-            __syncthreads();
-            {
-                const int excl = s_misc[wave] + incl - lsum;
-                for (int g = 0; g < gn; ++g) {
-                    const int tgt = s_tgt[g];
-                    if (tgt < excl || tgt >= excl + lsum) continue;
-                    int r = tgt - excl;
-                    for (int p = p0; p < p1; ++p) {
-                        const uint32_t q = s_q[p];
-                        const int cnt = __popc(q) >> 3;
-                        if (r >= cnt) {
-                            r -= cnt;
-                            continue;
-                        }
-                        for (int b2 = 0; b2 < 4; ++b2)
-                            if ((q >> (8 * b2)) & 0xFFu) {
-                                if (r == 0) {
-                                    s_cl[p] = 0xFFu << (8 * b2);
-                                    break;
-                                }
-                                --r;
-                            }
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            // growth of every slot's cluster until a pass adds nothing; a
-            // work item is one double column of one slot (icm_grow_column)
-            int grown = 1;
-            while (grown) {
-                int add = 0;
-                for (int it = tid; it < gn * G::NC; it += NT) {
-                    const int g = it / G::NC;
-                    add |= icm_grow_column<L, JF>(s_q + g * SDW, s_cl + g * SDW, s_nz, it - g * G::NC);
-                }
-                grown = __syncthreads_or(add);
-            }
-            // flip every cluster in both walkers of its slot
-            int fl = 0;
-            for (int p = p0; p < p1; ++p) {
-                const int g = p / SDW, w = p - g * SDW;
-                const uint32_t cl = s_cl[p];
-                if (!cl) continue;
-                s_spin[s_who[k0s + g] * SDW + w] ^= cl;
-                s_spin[s_who[T + k0s + g] * SDW + w] ^= cl;
-                fl += __popc(cl) >> 3;
-            }
-            for (int off = 32; off > 0; off >>= 1) fl += __shfl_xor(fl, off, 64);
-            if (lane == 0) s_misc[32 + wave] = fl;
-            if (tid < 2 * gn) s_E[s_who[(tid / gn) * T + k0s + tid % gn]] = 0;
-            __syncthreads();
-            // energies of the moved walkers
-            for (int u = tid; u < 2 * gn * G::NC; u += NT) {
-                const int pw = u / G::NC;
-                const int wk = s_who[(pw / gn) * T + k0s + pw % gn];
-                atomicAdd(&s_E[wk], Col::column_energy_of(s_spin + wk * SDW, s_j, u - pw * G::NC));
-            }
-            if (tid == 0) {
-                int tot_fl = 0;
-                for (int w = 0; w < kIcmNW; ++w) tot_fl += s_misc[32 + w];
-                s_misc[kIcmNW + 2] = tot_fl;
-            }
-            __syncthreads();
-            flipped += s_misc[kIcmNW + 2];
-            __syncthreads();
-        }
+        // ---- 2. cluster moves: slot k's by wave (k - icm_from) mod 12 ---------------
+        for (int k = job.icm_from + wave; k < T; k += kIcmNW)
+            icm_move_wave<L, JF>(s_spin, s_j, s_lm, s_wcl + wave * IcmBits<L>::ROW, s_who[k], s_who[T + k], k, t, chain, k0,
+                                 k1, lane, s_E, s_fl + k);
+        __syncthreads();
         // ---- 3. exchanges inside each copy ---------------------------------------
         if (tid < 2 * T) {
             const int cp = tid / T, k = tid - cp * T;
@@ -373,7 +411,11 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
             for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
             if (lane == 0) {
                 if (job.emin_trace) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = e;
-                if (job.icm_flipped) job.icm_flipped[static_cast<int64_t>(run) * job.n_steps + ti] = flipped;
+                if (job.icm_flipped) {
+                    int32_t flipped = 0;
+                    for (int k = job.icm_from; k < T; ++k) flipped += s_fl[k];
+                    job.icm_flipped[static_cast<int64_t>(run) * job.n_steps + ti] = flipped;
+                }
             }
         }
         __syncthreads();
@@ -401,21 +443,15 @@ static int launch_pticm(const PtIcmJob &job, int n_runs, uint32_t k0, uint32_t k
 {
     constexpr bool JF = false;   // E only in LDS: fewer coupling reads (as in PT)
     constexpr size_t kLds = 160 * 1024;
-    const size_t base = pticm_lds_bytes<L, JF>(job.T, 1);
-    if (base > kLds)
-        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, base);
-    // as many slots' cluster moves at once as the LDS left over holds
-    PtIcmJob jb = job;
-    const int slots = std::max(1, job.T - job.icm_from);
-    const size_t per_slot = 2 * static_cast<size_t>(Geo<L>::SPIN_DW) * 4;
-    jb.G = static_cast<int32_t>(std::min<size_t>(slots, 1 + (kLds - base) / per_slot));
-    const size_t bytes = pticm_lds_bytes<L, JF>(job.T, jb.G);
+    const size_t bytes = pticm_lds_bytes<L, JF>(job.T);
+    if (bytes > kLds)
+        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
     auto kern = k_pticm<L, JF>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: LDS attribute: %s", hipGetErrorString(err));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, jb, k0, k1);
+    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, job, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: launch failed: %s", hipGetErrorString(err));
     return SG_OK;
