@@ -399,8 +399,8 @@ def pticm(a, sg, wl, torch):
             "us_per_step": ms * 1e3 / steps, "sites_flipped_per_step_mean": fl,
             "roofline": {"bound": "alu", "achieved": 20 * rate / 1e12, "peak": peak, "unit": "T 32-bit VALU ops/s",
                          "frac": 20 * rate / 1e12 / peak,
-                         "note": "Metropolis work only (20 VALU slots per attempt); the cluster moves (block-wide "
-                                 "growth passes over double columns, a barrier each) are the larger part of a step"}}
+                         "note": "Metropolis work only (20 VALU slots per attempt); the cluster moves (one wave "
+                                 "per slot, breadth-first rounds on bit-packed double columns) take the rest of a step"}}
 
 
 def tuning(a, sg, wl, torch):

@@ -197,6 +197,15 @@ __device__ __forceinline__ uint32_t kb_addr(uint32_t kb)
     return __builtin_amdgcn_ubfe(kb, 8 * B - 2, 10);
 }
 
+// LDS a launch of kern may request dynamically: the compute unit's 160 KB
+// less what the kernel holds statically (host code)
+inline size_t lds_dynamic_cap(const void *kern)
+{
+    hipFuncAttributes a{};
+    const size_t stat = hipFuncGetAttributes(&a, kern) == hipSuccess ? a.sharedSizeBytes : 0;
+    return 160 * 1024 - stat;
+}
+
 // byte sum of a dword (an unsigned byte dot product with 1, 1, 1, 1)
 __device__ __forceinline__ uint32_t byte_sum(uint32_t v)
 {

@@ -467,6 +467,8 @@ static int launch_pt_cfg(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStr
                          size_t lds_cap = 160 * 1024)
 {
     using Cfg = PtCfg<L>;
+    auto kern = k_pt<L, NW, Cfg::JF, UMAX, SPLIT, WPE>;
+    lds_cap = std::min(lds_cap, lds_dynamic_cap(reinterpret_cast<const void *>(kern)));
     const int TG = job.T / job.G;
     const size_t base = pt_lds_bytes<L, Cfg::JF>(TG, job.T, 0);
     if (base > lds_cap)
@@ -480,7 +482,6 @@ static int launch_pt_cfg(PtJob job, int n_runs, uint32_t k0, uint32_t k1, hipStr
     if (UMAX > 0 && (units + NW * 64 - 1) / (NW * 64) > UMAX)
         return fail(SG_EUNSUPPORTED, "%s: %d units per colour exceed %d lanes x %d prepared units", who, units,
                     NW * 64, UMAX);
-    auto kern = k_pt<L, NW, Cfg::JF, UMAX, SPLIT, WPE>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "%s: LDS attribute: %s", who, hipGetErrorString(err));

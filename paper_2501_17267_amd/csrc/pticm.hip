@@ -34,10 +34,12 @@ struct PtIcmJob {
     int32_t *icm_flipped;   // [n_runs][n_steps] or NULL
     uint32_t run0;
     int32_t T, n_steps, step0, K, M, icm_from, init_random;
+    int32_t mx;             // exchange-table entries per ladder pair held in LDS
 };
 
 constexpr int kIcmNW = 12;          // 768 lanes per run
 constexpr int kIcmThr = kThrEntries;
+constexpr int kIcmMx = 128;        // exchange-table entries per pair staged in LDS (at most)
 
 // One slot's sites as bits.  Item col is the double column of index col:
 // both colour columns, i.e. the sites with x in {2k, 2k+1} at one y, every
@@ -76,13 +78,14 @@ struct IcmBits {
 // LDS of one run: walkers, couplings, thresholds, ladder words, the
 // nonzero-coupling masks (bytes, then bits) and one cluster row per wave
 template <int L, bool JF>
-constexpr size_t pticm_lds_bytes(int T)
+constexpr size_t pticm_lds_bytes(int T, int mx)
 {
     using G = Geo<L>;
     const size_t W = 2 * static_cast<size_t>(T);
     return (W * G::SPIN_DW + G::jdw_odd(JF ? 2 : 1) + static_cast<size_t>(T) * kIcmThr + 3 * W +
             2 * (static_cast<size_t>(T) - 1) + static_cast<size_t>(T) + 6 * static_cast<size_t>(G::SPIN_DW) +
-            7 * static_cast<size_t>(G::NC) + static_cast<size_t>(kIcmNW) * IcmBits<L>::ROW) * 4;
+            7 * static_cast<size_t>(G::NC) + static_cast<size_t>(kIcmNW) * IcmBits<L>::ROW +
+            static_cast<size_t>(T - 1) * static_cast<size_t>(mx)) * 4;
 }
 
 // Directions of the link masks (receiving site's coupling nonzero), kept
@@ -90,25 +93,21 @@ constexpr size_t pticm_lds_bytes(int T)
 // +z, -z, the x link inside the item, -x to item k-1, +x to item k+1, +y, -y
 enum : int { kLmZp = 0, kLmZm, kLmXin, kLmXm, kLmXp, kLmYp, kLmYm, kLmN };
 
+// wave-wide prefix sums and sums (the device library's, on DPP lane moves
+// instead of LDS round trips); every lane of the wave must take part
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ int __ockl_wfred_add_i32(int);
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+
 // exclusive prefix sum over the lanes of a wave, and the wave total
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total)
+__device__ __forceinline__ int wave_excl_scan(int v, int &total)
 {
-    int incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    total = __shfl(incl, 63, 64);
+    const int incl = __ockl_wfscan_add_i32(v, true);
+    total = __builtin_amdgcn_readlane(incl, 63);
     return incl - v;
 }
 
-__device__ __forceinline__ int wave_sum(int v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ int wave_sum(int v) { return __ockl_wfred_add_i32(v); }
 
 // position of the j-th set bit (j counted from 0) of f
 __device__ __forceinline__ uint32_t nth_bit(uint32_t f, int j)
@@ -162,13 +161,13 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
     int p0[NI], p1[NI], tot = 0, N0 = 0;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        p0[i] = N0 + wave_excl_scan(n0[i], lane, tot);
+        p0[i] = N0 + wave_excl_scan(n0[i], tot);
         N0 += tot;
     }
     int N1 = 0;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        p1[i] = N0 + N1 + wave_excl_scan(n1[i], lane, tot);
+        p1[i] = N0 + N1 + wave_excl_scan(n1[i], tot);
         N1 += tot;
     }
     const int n = N0 + N1;
@@ -243,19 +242,17 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
     size = wave_sum(size);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // 5. the two walkers' energies (Eq. 1) from their new spins
-    int ea = 0, eb = 0;
-    for (int u = lane; u < 2 * NC; u += 64) {
-        if (u < NC)
-            ea += Col::column_energy_of(sa, s_j, u);
-        else
-            eb += Col::column_energy_of(sb, s_j, u - NC);
-    }
+    // 5. energies (Eq. 1): wa's from its new spins; the move keeps the sum
+    // of the pair's energies (on a boundary bond of the cluster the two
+    // walkers agree at the outer site and disagree at the inner one, so the
+    // two bond terms cancel before and after), which gives wb's
+    int ea = 0;
+    for (int u = lane; u < NC; u += 64) ea += Col::column_energy_of(sa, s_j, u);
     ea = wave_sum(ea);
-    eb = wave_sum(eb);
     if (lane == 0) {
+        const int32_t pair = s_E[wa] + s_E[wb];
         s_E[wa] = ea;
-        s_E[wb] = eb;
+        s_E[wb] = pair - ea;
         *size_out = size;
     }
 }
@@ -281,6 +278,7 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     uint32_t *s_nz = reinterpret_cast<uint32_t *>(s_fl + T);  // [6][SDW] nonzero-coupling masks
     uint32_t *s_lm = s_nz + 6 * SDW;                         // [kLmN][NC] link masks as bits
     uint32_t *s_wcl = s_lm + kLmN * G::NC;                   // [kIcmNW][ROW] cluster rows
+    uint32_t *s_thrx = s_wcl + kIcmNW * IcmBits<L>::ROW;     // [T-1][mx] exchange thresholds
 
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = tid & 63, wave = tid >> 6;
@@ -302,6 +300,10 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
         s_who[tid] = -1;
     }
     if (tid < 2 * (T - 1)) s_sw[tid] = 0;
+    for (int w = tid; w < (T - 1) * job.mx; w += NT) {
+        const int k = w / job.mx, e = w - k * job.mx;
+        s_thrx[w] = job.thrx[static_cast<int64_t>(k) * job.M + e];
+    }
     load_couplings<L, JF, kColMajorOdd>(s_j, job.J, job.jenc, tid, NT);
     __syncthreads();
     if (tid < W && s_pos[tid] >= 0) s_who[(tid / T) * T + s_pos[tid]] = tid;
@@ -365,10 +367,31 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
     }
     __syncthreads();
 
+    // a lane's prepared sweep unit (when W * NC units fit the lanes)
+    const bool prep = W * G::NC <= NT;
+    const bool pact = tid < W * G::NC;
+    const int pwk = pact ? tid / G::NC : 0;
+    const typename Col::Unit pun =
+        Col::make_unit(pact ? tid - pwk * G::NC : 0, static_cast<uint32_t>(pwk), chain, k0, k1);
+
     for (int ti = 0; ti < job.n_steps; ++ti) {
         const uint32_t t = static_cast<uint32_t>(job.step0 + ti);
         // ---- 1. sweeps ----------------------------------------------------------
-        for (int c = 0; c < 2; ++c) {
+        if (prep) {
+            // one (walker, column) unit per lane, the same every step: its
+            // neighbours and the step-independent Philox products are kept
+            int32_t acc = 0;
+            const uint32_t *tbl = s_thr + s_pos[pwk] * kIcmThr;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (pact)
+                    acc += Col::template metropolis_unit<true>(s_spin + pwk * SDW, s_j, tbl, c, pun,
+                                                               2u * t + static_cast<uint32_t>(c), k0, k1);
+                if (c == 0) __syncthreads();
+            }
+            if (pact && acc != 0) atomicAdd(&s_E[pwk], acc);
+            __syncthreads();
+        } else for (int c = 0; c < 2; ++c) {
             for (int u = tid; u < W * G::NC; u += NT) {
                 const int wk = u / G::NC;
                 const int col = u - wk * G::NC;
@@ -388,13 +411,18 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
         if (tid < 2 * T) {
             const int cp = tid / T, k = tid - cp * T;
             if (k + 1 < T && ((k ^ static_cast<int>(t)) & 1) == 0) {
+                // the word is drawn before the energies are read: it depends
+                // on the counter alone
+                const uint32_t ux = philox10(static_cast<uint32_t>(k + cp * T), t, 0xFFFFFFFFu, chain, k0, k1).w[0];
                 const int a = s_who[cp * T + k], b = s_who[cp * T + k + 1];
                 const int32_t D = s_E[a] - s_E[b];
                 bool acc = D <= 0;
                 if (!acc) {
                     const int32_t m = D / 2;
-                    const Rand4 u = philox10(static_cast<uint32_t>(k + cp * T), t, 0xFFFFFFFFu, chain, k0, k1);
-                    acc = (m <= job.M) && (u.w[0] < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
+                    if (m <= job.mx)
+                        acc = ux < s_thrx[k * job.mx + (m - 1)];
+                    else
+                        acc = (m <= job.M) && (ux < job.thrx[static_cast<int64_t>(k) * job.M + (m - 1)]);
                 }
                 if (acc) {
                     s_who[cp * T + k] = b;
@@ -408,7 +436,7 @@ __global__ __launch_bounds__(kIcmNW * 64) void k_pticm(PtIcmJob job, uint32_t k0
         if (tid >= 64 && tid < 128) {
             int32_t e = 0x7FFFFFFF;
             for (int w = lane; w < W; w += 64) e = min(e, s_E[w]);
-            for (int off = 32; off > 0; off >>= 1) e = min(e, __shfl_xor(e, off, 64));
+            e = __ockl_wfred_min_i32(e);
             if (lane == 0) {
                 if (job.emin_trace) job.emin_trace[static_cast<int64_t>(run) * job.n_steps + ti] = e;
                 if (job.icm_flipped) {
@@ -442,16 +470,22 @@ template <int L>
 static int launch_pticm(const PtIcmJob &job, int n_runs, uint32_t k0, uint32_t k1, hipStream_t stream)
 {
     constexpr bool JF = false;   // E only in LDS: fewer coupling reads (as in PT)
-    constexpr size_t kLds = 160 * 1024;
-    const size_t bytes = pticm_lds_bytes<L, JF>(job.T);
-    if (bytes > kLds)
-        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, bytes);
     auto kern = k_pticm<L, JF>;
+    const size_t kLds = lds_dynamic_cap(reinterpret_cast<const void *>(kern));
+    const size_t base = pticm_lds_bytes<L, JF>(job.T, 0);
+    if (base > kLds)
+        return fail(SG_EUNSUPPORTED, "sg_pticm_run: L = %d with T = %d needs %zu bytes of LDS", L, job.T, base);
+    // the exchange-table prefix held in LDS: up to kIcmMx entries per pair,
+    // as many as the LDS left over allows (later entries are read from HBM)
+    PtIcmJob jb = job;
+    jb.mx = static_cast<int32_t>(std::min<size_t>({static_cast<size_t>(job.M), static_cast<size_t>(kIcmMx),
+                                                   (kLds - base) / (4 * static_cast<size_t>(job.T - 1))}));
+    const size_t bytes = pticm_lds_bytes<L, JF>(job.T, jb.mx);
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: LDS attribute: %s", hipGetErrorString(err));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, job, k0, k1);
+    hipLaunchKernelGGL(kern, dim3(n_runs), dim3(kIcmNW * 64), bytes, stream, jb, k0, k1);
     err = hipGetLastError();
     if (err != hipSuccess) return fail(SG_EDEVICE, "sg_pticm_run: launch failed: %s", hipGetErrorString(err));
     return SG_OK;
