@@ -157,6 +157,7 @@ struct Geo {
     static constexpr int N = L * L * L;
     static constexpr int JDW_EF = 2 * NC * 6 * 2 * C;  // encoded couplings, E and F
     static constexpr int JDW_E = 2 * NC * 6 * C;       // encoded couplings, E only
+    static constexpr int JDW_3E = 2 * NC * 3 * C;      // E only, forward directions only
     // The odd-stride LDS arrangement of the couplings (kColMajorOdd, with hn
     // halves per direction): where a column's 6*hn*C dwords sit side by
     // side (jside: not 4-dword columns, nor hn*C = 2 or 4), the stride from

@@ -38,16 +38,21 @@ static const SaVariant kV20[] = {SG_V(20, 6, 12, true), SG_V(20, 8, 5, false), S
 static const SaVariant kV22[] = {SG_V(22, 4, 8, false), SG_V(22, 4, 16, false), SG_V(22, 1, 4, true)};
 static const SaVariant kV24[] = {SG_V(24, 4, 9, false), SG_V(24, 4, 6, false), SG_V(24, 1, 5, false),
                                  SG_V(24, 3, 14, false)};
-// couplings streamed from HBM (L2-resident), spins in LDS; at L = 26 and 28 also
-// one or two replicas with the couplings' E bytes in LDS (F formed per use)
+// spins in LDS; couplings streamed from HBM (L2-resident), or in LDS as E
+// bytes (F formed per use) of all six directions (L = 26, 28: one or two
+// replicas) or of the three forward ones (more replicas, up to L = 32)
 static const SaVariant kV26[] = {SG_VX(26, 2, 11, kJGlobalEF, true), SG_VX(26, 1, 6, kJGlobalEF, true),
                                  SG_VX(26, 4, 11, kJGlobalEF, true), SG_VX(26, 1, 6, kJLdsE, true),
-                                 SG_VX(26, 1, 8, kJLdsE, true), SG_VX(26, 2, 11, kJLdsE, true)};
+                                 SG_VX(26, 1, 8, kJLdsE, true), SG_VX(26, 2, 11, kJLdsE, true),
+                                 SG_VX(26, 2, 11, kJLds3E, true), SG_VX(26, 4, 11, kJLds3E, true)};
 static const SaVariant kV28[] = {SG_VX(28, 2, 13, kJGlobalEF, true), SG_VX(28, 1, 7, kJGlobalEF, true),
                                  SG_VX(28, 4, 13, kJGlobalEF, true), SG_VX(28, 1, 7, kJLdsE, true),
-                                 SG_VX(28, 1, 8, kJLdsE, true)};
-static const SaVariant kV30[] = {SG_VX(30, 2, 15, kJGlobalEF, true), SG_VX(30, 1, 8, kJGlobalEF, true)};
-static const SaVariant kV32[] = {SG_VX(32, 2, 16, kJGlobalEF, true), SG_VX(32, 1, 8, kJGlobalEF, true)};
+                                 SG_VX(28, 1, 8, kJLdsE, true), SG_VX(28, 2, 13, kJLds3E, true),
+                                 SG_VX(28, 4, 13, kJLds3E, true)};
+static const SaVariant kV30[] = {SG_VX(30, 2, 15, kJGlobalEF, true), SG_VX(30, 1, 8, kJGlobalEF, true),
+                                 SG_VX(30, 1, 8, kJLds3E, true), SG_VX(30, 2, 15, kJLds3E, true)};
+static const SaVariant kV32[] = {SG_VX(32, 1, 8, kJLds3E, true), SG_VX(32, 2, 16, kJGlobalEF, true),
+                                 SG_VX(32, 1, 8, kJGlobalEF, true)};
 // couplings and spins both in HBM (a global spin workspace per replica);
 // L = 34..62 are in sa_large.hip
 static const SaVariant kV64[] = {SG_VX(64, 1, 16, kJGlobalEF, false), SG_VX(64, 1, 8, kJGlobalEF, false)};

@@ -30,7 +30,8 @@ struct SaJob {
 enum : int {
     kJLdsEF = 0,    // LDS, both encodings E = J + 8 and F = 8 - J
     kJLdsE = 1,     // LDS, E only (F = 16 - E computed per use)
-    kJGlobalEF = 2  // streamed from the encoded HBM buffer (jenc), E and F
+    kJGlobalEF = 2, // streamed from the encoded HBM buffer (jenc), E and F
+    kJLds3E = 3     // LDS, E of the three forward directions (backward ones from the neighbours)
 };
 
 // A replica group inside a job (batched launches: one work group each).
@@ -43,14 +44,14 @@ template <int L, int RPW, int NW, int JM, bool SPIN_LDS, bool TRACK>
 __device__ void sa_group(const SaJob &job, int group, uint32_t k0, uint32_t k1)
 {
     using G = Geo<L>;
-    constexpr bool JF = (JM != kJLdsE);
+    constexpr bool JF = (JM != kJLdsE && JM != kJLds3E);
     // LDS arrays column-major (spin columns of 3, 5 or 6 dwords split in
     // two planes), HBM arrays dword-major (coalesced)
     constexpr int SLAY = SPIN_LDS ? (G::SPLIT_COLUMNS ? kColSplit : kColMajor) : kDwordMajor;
-    constexpr int JLAY = (JM == kJGlobalEF) ? kDwordMajor : kColMajor;
+    constexpr int JLAY = (JM == kJGlobalEF) ? kDwordMajor : (JM == kJLds3E ? kFwd3 : kColMajor);
     using Col = Column<L, JF, SLAY, JLAY>;
     constexpr int NT = NW * 64;
-    constexpr int JDW = (JM == kJGlobalEF) ? 0 : (JF ? G::JDW_EF : G::JDW_E);
+    constexpr int JDW = (JM == kJGlobalEF) ? 0 : (JM == kJLds3E ? G::JDW_3E : (JF ? G::JDW_EF : G::JDW_E));
     constexpr int SDW = SPIN_LDS ? RPW * G::SPIN_DW : 0;
     // One LDS block: the two threshold tables first (fixed addresses 0 and
     // 256 bytes, so table lookups need no base register), then per-replica

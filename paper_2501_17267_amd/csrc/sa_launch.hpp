@@ -41,12 +41,12 @@ template <int L, int JM, bool SL>
 constexpr size_t lds_of(int rpw)
 {
     using G = Geo<L>;
-    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsE ? G::JDW_E : G::JDW_EF);
+    const int jdw = (JM == kJGlobalEF) ? 0 : (JM == kJLdsE ? G::JDW_E : (JM == kJLds3E ? G::JDW_3E : G::JDW_EF));
     return 4 * (((2 * kThrEntries + 3 * rpw + 3) & ~3) + jdw + (SL ? rpw * G::SPIN_DW : 0));
 }
 
 #define SG_VX(L, RPW, NW, JM, SL) \
-    {L, RPW, NW, (JM) == kJLdsE ? 0 : 1, (JM) == kJGlobalEF ? 1 : 0, SL ? 0 : 1, lds_of<L, JM, SL>(RPW), \
+    {L, RPW, NW, ((JM) == kJLdsE || (JM) == kJLds3E) ? 0 : 1, (JM) == kJGlobalEF ? 1 : 0, SL ? 0 : 1, lds_of<L, JM, SL>(RPW), \
      &launch_variant<L, RPW, NW, JM, SL>}
 #define SG_V(L, RPW, NW, JF) SG_VX(L, RPW, NW, (JF) ? kJLdsEF : kJLdsE, true)
 

@@ -20,7 +20,7 @@
 
 namespace sg {
 
-enum Layout : int { kColMajor = 0, kDwordMajor = 1, kColMajorOdd = 2, kColSplit = 3 };
+enum Layout : int { kColMajor = 0, kDwordMajor = 1, kColMajorOdd = 2, kColSplit = 3, kFwd3 = 4 };
 
 // kColSplit (spins in LDS, columns of C = 3, 5 or 6 dwords): the first CA
 // dwords of every column (CA = 2 or 4) in one plane, CA dwords per column,
@@ -69,10 +69,15 @@ static_assert(Geo<12>::jside(1) && Geo<12>::jstride_odd(1) == 19 && !Geo<16>::js
                   Geo<10>::jside(2),
               "Geo::jside is mode 2 of lds_jmode");
 
+// kFwd3 (couplings in LDS for lattices whose six directions would not fit):
+// E bytes of the three forward directions only (d = 0, 2, 4: +x, +y, +z),
+// dword-major; a site's backward coupling is its backward neighbour's
+// forward one (Column::field_sum).
 template <int L, int HN, int LAY>
 __device__ __forceinline__ int coupling_at(int c, int col, int d, int h, int m)
 {
     using G = Geo<L>;
+    if (LAY == kFwd3) return ((c * 3 + d / 2) * G::C + m) * G::NC + col;
     if (LAY == kDwordMajor) return (((c * 6 + d) * HN + h) * G::C + m) * G::NC + col;
     constexpr int mode = lds_jmode<L, HN>();
     if (mode == 0) return (((c * 6 + d) * HN + h) * G::NC + col) * G::C + m;
@@ -121,10 +126,36 @@ struct Column {
         return n;
     }
 
-    // sum over the six directions of 8 + J s_nbr, per byte
-    __device__ static uint32_t field_sum(const uint32_t *jl, int c, int col, int m, const uint32_t (&nb)[6])
+    // sum over the six directions of 8 + J s_nbr, per byte (n: the column's
+    // neighbours, as seen from colour c)
+    __device__ static uint32_t field_sum(const uint32_t *jl, int c, int col, int m, const uint32_t (&nb)[6],
+                                         const Nbr &n)
     {
         uint32_t V = 0;
+        if constexpr (JLAY == kFwd3) {
+            static_assert(!JF, "the forward-only arrangement holds E only");
+            // backward couplings from the other colour's columns, as the
+            // backward neighbour spins are gathered: -x from column k-1 where
+            // x is even and from the same index where it is odd, -y from
+            // y-1, -z from the site below (one byte down the same column)
+            const int oc = c ^ 1;
+            uint32_t E[6];
+            E[0] = jl[coupling_at<L, 1, kFwd3>(c, col, 0, 0, m)];
+            E[2] = jl[coupling_at<L, 1, kFwd3>(c, col, 2, 0, m)];
+            E[4] = jl[coupling_at<L, 1, kFwd3>(c, col, 4, 0, m)];
+            E[1] = bfi(n.even_x, jl[coupling_at<L, 1, kFwd3>(oc, n.xm, 0, 0, m)],
+                       jl[coupling_at<L, 1, kFwd3>(oc, n.self, 0, 0, m)]);
+            E[3] = jl[coupling_at<L, 1, kFwd3>(oc, n.ym, 2, 0, m)];
+            const uint32_t zc = jl[coupling_at<L, 1, kFwd3>(oc, n.self, 4, 0, m)];
+            if (G::TAIL != 0 && m == 0)
+                E[5] = __builtin_amdgcn_perm(zc, jl[coupling_at<L, 1, kFwd3>(oc, n.self, 4, 0, C - 1)], 0x06050401u);
+            else
+                E[5] = __builtin_amdgcn_alignbyte(zc, jl[coupling_at<L, 1, kFwd3>(oc, n.self, 4, 0, m > 0 ? m - 1 : C - 1)],
+                                                  3);
+#pragma unroll
+            for (int d = 0; d < 6; ++d) V += bfi(nb[d], 0x10101010u - E[d], E[d]);
+            return V;
+        }
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
             const uint32_t E = jl[coupling_at<L, HN, JLAY>(c, col, d, 0, m)];
@@ -168,7 +199,7 @@ struct Column {
             else
                 zm = __builtin_amdgcn_alignbyte(sv[m], sv[(m + C - 1) % C], 3);
             const uint32_t nb[6] = {bfi(n.even_x, sv[m], xp[m]), bfi(n.even_x, xm[m], sv[m]), yv[m], ymv[m], zp, zm};
-            kb[m] = field_to_kb(own[m], field_sum(jl, c, col, m, nb));
+            kb[m] = field_to_kb(own[m], field_sum(jl, c, col, m, nb, n));
         }
     }
 
@@ -176,9 +207,8 @@ struct Column {
     // dword m of colour-c column col, gathered from the colour-(1-c)
     // columns of a byte array in the column layout (spins, or any per-site
     // byte mask laid out the same way)
-    __device__ static void nbr_dwords(const uint32_t *rep, int c, int col, int m, uint32_t (&nb)[6])
+    __device__ static void nbr_dwords_n(const uint32_t *rep, int c, const Nbr &n, int m, uint32_t (&nb)[6])
     {
-        const Nbr n = neighbours(c, col);
         const int oc = c ^ 1;
         const uint32_t s_m = rep[spin_at<L, SLAY>(oc, n.self, m)];
         uint32_t zp, zm;
@@ -205,8 +235,9 @@ struct Column {
                                            uint32_t own_m)
     {
         uint32_t nb[6];
-        nbr_dwords(rep, c, col, m, nb);
-        return field_to_kb(own_m, field_sum(jl, c, col, m, nb));
+        const Nbr n = neighbours(c, col);
+        nbr_dwords_n(rep, c, n, m, nb);
+        return field_to_kb(own_m, field_sum(jl, c, col, m, nb, n));
     }
 
     // 0xFF in every byte of dword m of colour-c column col whose coupling in
@@ -421,11 +452,12 @@ __device__ void load_couplings(uint32_t *jl, const int8_t *J, const uint32_t *je
     using G = Geo<L>;
     constexpr int C = G::C;
     constexpr int HN = JF ? 2 : 1;
-    for (int w = tid; w < 2 * G::NC * 6 * C; w += nt) {
+    constexpr int ND = JLAY == kFwd3 ? 3 : 6;   // directions held (forward only: d = 0, 2, 4)
+    for (int w = tid; w < 2 * G::NC * ND * C; w += nt) {
         const int m = w % C;
         int t = w / C;
-        const int d = t % 6;
-        t /= 6;
+        const int d = JLAY == kFwd3 ? 2 * (t % 3) : t % 6;
+        t /= ND;
         const int col = t % G::NC;
         const int c = t / G::NC;
         uint32_t e, f;
