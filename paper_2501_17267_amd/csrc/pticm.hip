@@ -93,6 +93,10 @@ constexpr size_t pticm_lds_bytes(int T, int mx)
 // +z, -z, the x link inside the item, -x to item k-1, +x to item k+1, +y, -y
 enum : int { kLmZp = 0, kLmZm, kLmXin, kLmXm, kLmXp, kLmYp, kLmYm, kLmN };
 
+// hops inside an item per breadth-first round, after the hop that reads the
+// neighbouring items
+constexpr int kIcmInnerHops = 1;
+
 // wave-wide prefix sums and sums (the device library's, on DPP lane moves
 // instead of LDS round trips); every lane of the wave must take part
 extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
@@ -211,8 +215,15 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
             uint32_t A = (B::down(own) & msk[i][kLmZp]) | (B::up(own) & msk[i][kLmZm]) | (own & msk[i][kLmXin]);
             A |= (a & msk[i][kLmXm]) | (b & msk[i][kLmXp]) | (c & msk[i][kLmYp]) | (d & msk[i][kLmYm]);
             const uint32_t nw = B::swap(A) & q[i] & ~own;
-            cl[i] = own | nw;
-            grown |= nw;
+            // then kIcmInnerHops more hops inside the item (z links and the
+            // inner x link), which need no other lane
+            uint32_t cur = own | nw;
+#pragma unroll
+            for (int h = 0; h < kIcmInnerHops; ++h)
+                cur |= B::swap((B::down(cur) & msk[i][kLmZp]) | (B::up(cur) & msk[i][kLmZm]) |
+                               (cur & msk[i][kLmXin])) & q[i];
+            cl[i] = cur;
+            grown |= cur ^ own;
         }
 #pragma unroll
         for (int i = 0; i < NI; ++i) wcl[lane + 64 * i] = cl[i];
