@@ -455,9 +455,7 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
                     v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
                     m = fmax(m, static_cast<double>(v));
                 }
-                // streamed out: the next read of this entry is the next
-                // step's, after the whole table has passed through the caches
-                __builtin_nontemporal_store(v, &tab[O]);
+                tab[O] = v;
                 c = (c - nm) & nm;
             } while (c != 0);
         }
