@@ -376,6 +376,22 @@ int sg_tn_plan_destroy(sg_tn_plan *plan);
 int sg_tn_plan_program(const sg_tn_plan *plan, int32_t *n_shapes, int32_t *shapes, int32_t *n_steps,
                        int32_t *steps, int32_t *n_items, int32_t *items);
 
+/* The plan's rounds, for inspection (host memory; either array may be NULL,
+ * the count is always written).  A round is one step of a shape or two
+ * consecutive ones that the workspace tier runs in one pass over the table
+ * (sum-product tables are renormalised after each round, in both tiers):
+ *   shape_rounds [n_shapes][2]: the shape's first round and round count;
+ *   rounds [n_rounds][4]: the first step (within its shape), 1 when the
+ *     round also runs the next step, the canonical read bits of the round
+ *     (assignments read = 2^bits), and the case of the second step's slot b
+ *     (0: b takes its slot at that step, 1: b is canonical at the first
+ *     step, 2: b becomes active at the first step) | b's rank among the
+ *     first step's canonical bits << 8.
+ * Pairs run fused only when beta <= SG_TN_FUSE_BETA_MAX or in the tropical
+ * form; otherwise every step is its own round. */
+#define SG_TN_FUSE_BETA_MAX 9.5
+int sg_tn_plan_rounds(const sg_tn_plan *plan, int32_t *n_rounds, int32_t *shape_rounds, int32_t *rounds);
+
 /* Workspace for n_inst instances: `full` = 0 gives the least that works
  * (the workspace tables are then processed in several passes), 1 the size
  * that holds the largest phase of all instances at once. */
@@ -385,7 +401,7 @@ typedef struct sg_tn_args {
     const int8_t *J;     /* device int8 [n_inst][6][N], values in [-4, 4] */
     int32_t n_inst;      /* instances of the plan's L decimated together */
     int32_t tropical;    /* 1: min-plus form (beta unused) */
-    double beta;         /* inverse temperature, 0 < beta <= 20 */
+    double beta;         /* inverse temperature, 0 < beta <= 14 (no overflow for |h| <= 24) */
     int8_t *spins_out;   /* device int8 [n_inst][N]: the decimated spins */
     double *score_out;   /* device double [n_inst][N] or NULL: each site's
                             ln Z(+1) - ln Z(-1), or E(-1) - E(+1) when tropical */

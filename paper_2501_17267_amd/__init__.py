@@ -168,6 +168,7 @@ def lib() -> ctypes.CDLL:
     L.sg_tn_plan_info_get.argtypes = [vp, c.POINTER(sg_tn_plan_info)]
     L.sg_tn_plan_destroy.argtypes = [vp]
     L.sg_tn_plan_program.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.sg_tn_plan_rounds.argtypes = [vp, vp, vp, vp]
     L.sg_tn_workspace_bytes.argtypes = [vp, c.c_int32, c.c_int32]
     L.sg_tn_workspace_bytes.restype = c.c_int64
     L.sg_tn_decimate.argtypes = [vp, c.POINTER(sg_tn_args), vp]
@@ -189,7 +190,7 @@ def lib() -> ctypes.CDLL:
                "sg_batch_destroy", "sg_make_schedule", "sg_make_thresholds", "sg_make_exchange_thresholds",
                "sg_make_instance", "sg_encode_instance", "sg_check_instance", "sa_anneal", "sg_sa_anneal_wide",
                "sg_fragment_decimate", "sg_pticm_run", "sg_tn_plan_create", "sg_tn_plan_info_get",
-               "sg_tn_plan_destroy", "sg_tn_plan_program", "sg_tn_decimate",
+               "sg_tn_plan_destroy", "sg_tn_plan_program", "sg_tn_plan_rounds", "sg_tn_decimate",
                "pt_run", "sg_pt_run_split", "energy", "epsilon"):
         getattr(L, fn).restype = c.c_int
     _lib = L
@@ -608,6 +609,18 @@ class TnPlan:
         _check(lib().sg_tn_plan_program(self._h, ctypes.byref(ns), _np_ptr(shapes), ctypes.byref(nt),
                                         _np_ptr(steps), ctypes.byref(ni), _np_ptr(items)), "sg_tn_plan_program")
         return shapes, steps[:nt.value], items
+
+    def rounds(self):
+        """(shape_rounds [S][2] int32: first round and count per shape,
+        rounds [R][4] int32: first step within the shape, fused, read bits,
+        slot case of the second step | its rank << 8)."""
+        nr = ctypes.c_int32()
+        _check(lib().sg_tn_plan_rounds(self._h, ctypes.byref(nr), None, None), "sg_tn_plan_rounds")
+        shape_rounds = np.zeros((self.info()["n_shapes"], 2), np.int32)
+        rounds = np.zeros((max(nr.value, 1), 4), np.int32)
+        _check(lib().sg_tn_plan_rounds(self._h, ctypes.byref(nr), _np_ptr(shape_rounds), _np_ptr(rounds)),
+               "sg_tn_plan_rounds")
+        return shape_rounds, rounds[:nr.value]
 
     def workspace_bytes(self, n_inst: int, full: bool = True) -> int:
         n = int(lib().sg_tn_workspace_bytes(self._h, n_inst, 1 if full else 0))

@@ -6,12 +6,14 @@
 // int32 for the tropical form) and runs the whole elimination program of
 // its shape, one block barrier per eliminated spin.
 // Workspace tier: larger tables live in the caller's workspace; every
-// elimination step is one launch over all tables of a batch that updates only
-// the canonical entries of its table (see TnStep), up to kTnPairsPerThread
-// reads per thread.
-// A sum-product table is renormalised after every step by the power of two
+// round (one elimination step, or two fused, see TnRound) is one launch over
+// all tables of a batch that updates only the canonical entries of its table
+// (see TnStep), up to kTnPairsPerThread read assignments per thread.
+// A sum-product table is renormalised after every round by the power of two
 // that brings its largest entry into [1, 2) (exact scaling, the exponents
-// summed beside it), so no table overflows or underflows for beta <= 20.
+// summed beside it).  With |h| <= kTnHMax no product overflows for
+// beta <= 14 when every step is a round, and for beta <= 9.5 with fused
+// rounds (raw values below 8 exp(2 kTnHMax beta) before a round's scale).
 // A decision kernel per phase turns the two results of each site into its
 // spin and score.
 #include <hip/hip_runtime.h>
@@ -44,11 +46,13 @@ struct TnJob {
     double *score;         // [n_inst][N] or null
     const TnShape *shapes;
     const TnStep *steps;
+    const TnRound *rounds;
     const TnItem *items;
     double *res;           // [n_inst][items of the phase][2]
     int32_t L, h, l;
     int64_t N;
     double beta;
+    int32_t fuse;          // 1: the plan's rounds, 0: one step per round
 };
 
 // the eliminated spin's slot, its active neighbours' slots and couplings, and
@@ -203,36 +207,48 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_lds(TnJob jb, TnWeights wt, i
     const int half = W > 0 ? 1 << (W - 1) : 0;
     double scale = 1.0;
     int e_prev = 0, e_sum = 0;
-    for (int t = 0; t < ns; ++t) {
-        if (!TROP && t > 0) {
+    // renormalised after every round, as the workspace tier is
+    const int nr = jb.fuse ? sh.n_rounds : ns;
+    for (int r = 0; r < nr; ++r) {
+        int t0 = r, n_sub = 1;
+        if (jb.fuse) {
+            const TnRound R = jb.rounds[sh.round0 + r];
+            t0 = R.step;
+            n_sub = 1 + R.fused;
+        }
+        if (!TROP && r > 0) {
             e_sum += e_prev;
             scale = ldexp(1.0, -e_prev);
         }
-        const TnDesc D = desc[t];
-        const uint32_t abit = 1u << D.a;
-        double m = 0.0;
-        for (int p = tid; p < half; p += kTnThreads) {
-            const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
-            const int hh = tn_field(D, I0);
-            T v;
-            if (TROP) {
-                v = min(tab[I0] + hh, tab[I1] - hh);
-            } else {
-                v = tn_pair_sum(tab[I0], w[kTnHMax + hh], tab[I1], w[kTnHMax - hh], scale);
-                m = fmax(m, static_cast<double>(v));
+        for (int t = t0; t < t0 + n_sub; ++t) {
+            const double sc_t = t == t0 ? scale : 1.0;
+            const TnDesc D = desc[t];
+            const uint32_t abit = 1u << D.a;
+            double m = 0.0;
+            for (int p = tid; p < half; p += kTnThreads) {
+                const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
+                const int hh = tn_field(D, I0);
+                T v;
+                if (TROP) {
+                    v = min(tab[I0] + hh, tab[I1] - hh);
+                } else {
+                    v = tn_pair_sum(tab[I0], w[kTnHMax + hh], tab[I1], w[kTnHMax - hh], sc_t);
+                    m = fmax(m, static_cast<double>(v));
+                }
+                tab[I0] = v;
+                tab[I1] = v;
             }
-            tab[I0] = v;
-            tab[I1] = v;
-        }
-        if (!TROP) {
-            const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
-            if ((tid & 63) == 0) s_emax[(t & 1) * (kTnThreads / 64) + (tid >> 6)] = e;
-        }
-        __syncthreads();
-        if (!TROP) {
-            int e = INT_MIN;
-            for (int i = 0; i < kTnThreads / 64; ++i) e = max(e, s_emax[(t & 1) * (kTnThreads / 64) + i]);
-            e_prev = e;
+            // the exponent after the round's last step is the one kept
+            if (!TROP) {
+                const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
+                if ((tid & 63) == 0) s_emax[(t & 1) * (kTnThreads / 64) + (tid >> 6)] = e;
+            }
+            __syncthreads();
+            if (!TROP) {
+                int e = INT_MIN;
+                for (int i = 0; i < kTnThreads / 64; ++i) e = max(e, s_emax[(t & 1) * (kTnThreads / 64) + i]);
+                e_prev = e;
+            }
         }
     }
     if (tid == 0) {
@@ -256,36 +272,51 @@ struct TnBatch {
     int32_t res_k0;             // position of that item among the phase's items
     int32_t n_items_q;
     int32_t k0, k1, b0, nb;
-    int32_t steps;              // row length of desc and emax
+    int32_t steps;              // row length of desc and emax (rounds <= steps)
     const int64_t *entry_pre;   // the phase's segment of the table-entry prefix
     int64_t ents_per_inst;
     struct TnTab *tabs;         // [tables]
-    struct TnDescX *desc;       // [tables][steps]
-    int32_t *blkpre;            // [steps][k1 - k0 + 1]: work groups of the items before
+    struct TnDescX *desc;       // [tables][rounds]
+    int32_t *blkpre;            // [rounds][k1 - k0 + 1]: work groups of the items before
                                 //   (one table; every instance and value has the same)
-    int32_t *emax;              // [tables][steps]
+    int32_t *emax;              // [tables][rounds]
     int32_t *es;                // [tables]
     void *tables;
 };
 
 struct TnTab {
-    int32_t n_steps, W;
+    int32_t n_rounds, W;
     int64_t off;                // first entry of the table in the batch's table region
 };
 
-// one elimination step of one workspace table, ready to use: the field
-// terms of the eliminated spin and the canonical bookkeeping of TnStep
+// one round of one workspace table, ready to use: the field terms of the
+// eliminated spin and the canonical bookkeeping of its first step (TnStep),
+// and for a fused round the second step's field terms, new slots and the
+// case of its slot b (TnRound)
 struct __align__(16) TnDescX {
     TnDesc d;
     uint32_t newmask;
-    uint8_t a_active, n_runs, n_base, pad;
+    uint8_t a_active, n_runs, n_base, fused;
     uint8_t run_start[8];
     uint8_t run_len[8];
-    uint32_t pad2[2];
+    TnDesc d1;
+    uint32_t newmask1;
+    uint8_t b_mode, b_rank, read_bits, pad;
 };
-static_assert(sizeof(TnDescX) == 48, "TnDescX layout");
+static_assert(sizeof(TnDescX) == 64, "TnDescX layout");
 
-// per (table, step): the step's descriptor; per table: its header, the
+// the round r of a shape: its first step and whether it is fused
+__device__ __host__ inline TnRound tn_round(const TnRound *rounds, const TnStep *steps, const TnShape &sh, int r,
+                                            bool fuse)
+{
+    if (fuse) return rounds[sh.round0 + r];
+    TnRound R{};
+    R.step = static_cast<int16_t>(r);
+    R.read_bits = steps[sh.step0 + r].n_base;
+    return R;
+}
+
+// per (table, round): the round's descriptor; per table: its header, the
 // centre's fixed-bond energy, and the exponent slots cleared
 __global__ void k_tn_hbm_prep(TnJob jb, TnBatch bt)
 {
@@ -306,15 +337,16 @@ __global__ void k_tn_hbm_prep(TnJob jb, TnBatch bt)
     bt.emax[gid] = INT_MIN;
     if (t == 0) {
         TnTab tb;
-        tb.n_steps = sh.n_steps;
+        tb.n_rounds = jb.fuse ? sh.n_rounds : sh.n_steps;
         tb.W = sh.W;
         tb.off = static_cast<int64_t>(bi) * bt.ents_per_inst + (bt.entry_pre[k] - bt.entry_pre[bt.k0]) +
                  (static_cast<int64_t>(cv) << sh.W);
         bt.tabs[tix] = tb;
         bt.es[tix] = tn_centre_energy(jb, J, dec, it.site, cv ? -1 : 1, sh);
     }
-    if (t < sh.n_steps) {
-        const TnStep st = jb.steps[sh.step0 + t];
+    if (t < (jb.fuse ? sh.n_rounds : sh.n_steps)) {
+        const TnRound R = tn_round(jb.rounds, jb.steps, sh, t, jb.fuse);
+        const TnStep st = jb.steps[sh.step0 + R.step];
         TnDescX x{};
         x.d = tn_desc(jb, J, dec, it.site, cv ? -1 : 1, st);
         x.newmask = st.newmask;
@@ -325,12 +357,21 @@ __global__ void k_tn_hbm_prep(TnJob jb, TnBatch bt)
             x.run_start[r] = st.run_start[r];
             x.run_len[r] = st.run_len[r];
         }
+        x.fused = R.fused;
+        x.read_bits = R.read_bits;
+        if (R.fused) {
+            const TnStep s1 = jb.steps[sh.step0 + R.step + 1];
+            x.d1 = tn_desc(jb, J, dec, it.site, cv ? -1 : 1, s1);
+            x.newmask1 = s1.newmask;
+            x.b_mode = R.b_mode;
+            x.b_rank = R.b_rank;
+        }
         bt.desc[gid] = x;
     }
 }
 
-// per step: the prefix over the batch's items of their work groups
-// (tn_table_blocks of the step's canonical reads; none once an item is done)
+// per round: the prefix over the batch's items of their work groups
+// (tn_table_blocks of the round's canonical reads; none once an item is done)
 __global__ void k_tn_hbm_blocks(TnJob jb, TnBatch bt)
 {
     const int t = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -341,7 +382,8 @@ __global__ void k_tn_hbm_blocks(TnJob jb, TnBatch bt)
     for (int kk = 0; kk < nk; ++kk) {
         bt.blkpre[t * (nk + 1) + kk] = acc;
         const TnShape sh = jb.shapes[jb.items[bt.item_hbm0 + bt.k0 + kk].shape];
-        if (t < sh.n_steps) acc += ((1 << jb.steps[sh.step0 + t].n_base) + per - 1) / per;
+        if (t < (jb.fuse ? sh.n_rounds : sh.n_steps))
+            acc += ((1 << tn_round(jb.rounds, jb.steps, sh, t, jb.fuse).read_bits) + per - 1) / per;
     }
     bt.blkpre[t * (nk + 1) + nk] = acc;
 }
@@ -349,17 +391,30 @@ __global__ void k_tn_hbm_blocks(TnJob jb, TnBatch bt)
 // canonical index of read item p: the bits of p deposited into the step's runs
 __device__ inline uint32_t tn_deposit(uint32_t p, const TnDescX &x)
 {
+    // the runs as two packed words (shifts rather than indexed bytes)
+    uint64_t starts, lens;
+    __builtin_memcpy(&starts, x.run_start, 8);
+    __builtin_memcpy(&lens, x.run_len, 8);
     uint32_t I = 0;
     int used = 0;
     for (int r = 0; r < x.n_runs; ++r) {
-        const int len = x.run_len[r];
-        I |= ((p >> used) & ((1u << len) - 1u)) << x.run_start[r];
+        const int len = static_cast<int>((lens >> (8 * r)) & 0xFFu);
+        I |= ((p >> used) & ((1u << len) - 1u)) << static_cast<int>((starts >> (8 * r)) & 0xFFu);
         used += len;
     }
     return I;
 }
 
-// step t of every table of the batch that has one: blocks_t work groups per
+// the bits of v at the set bits of mask, packed from bit 0 in increasing order
+__device__ inline uint32_t tn_extract(uint32_t v, uint32_t mask)
+{
+    uint32_t r = 0;
+    int k = 0;
+    for (uint32_t b = mask; b; b &= b - 1) r |= ((v >> __builtin_ctz(b)) & 1u) << k++;
+    return r;
+}
+
+// round t of every table of the batch that has one: blocks_t work groups per
 // (instance, centre value), each item's share given by the prefix blkpre[t]
 template <bool TROP>
 __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeights wt, int t, int blocks_t)
@@ -369,11 +424,12 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     __shared__ int s_emax[kTnThreads / 64];
     __shared__ int32_t pre[kTnThreads + 1];
     __shared__ int32_t s_hn[64];   // field from the new slots, per combination
+    __shared__ T s_v[kTnFuseMax][kTnThreads];   // a fused round's values between its steps
     const int tid = static_cast<int>(threadIdx.x);
     const int nk = bt.k1 - bt.k0;
     const int64_t g = static_cast<int64_t>(blockIdx.x) / blocks_t;   // (instance, value)
     const int rb = static_cast<int>(static_cast<int64_t>(blockIdx.x) - g * blocks_t);
-    // the step's prefix row, staged in LDS (batches have at most kTnThreads items)
+    // the round's prefix row, staged in LDS (batches have at most kTnThreads items)
     const int32_t *row = bt.blkpre + static_cast<int64_t>(t) * (nk + 1);
     for (int i = tid; i <= nk; i += kTnThreads) pre[i] = row[i];
     if (!TROP)
@@ -394,70 +450,137 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     const TnDescX x = bt.desc[tix * bt.steps + t];
     T *tab = reinterpret_cast<T *>(bt.tables) + tb.off;
     const double scale = (!TROP && t > 0) ? ldexp(1.0, -bt.emax[tix * bt.steps + t - 1]) : 1.0;
-    const int64_t items = int64_t{1} << x.n_base;
+    const int64_t items = int64_t{1} << x.read_bits;
     const int64_t stride = static_cast<int64_t>(bpt) * kTnThreads;
     const uint32_t abit = 1u << x.d.a;
     const uint32_t nm = x.newmask;
-    // the field splits into the part from canonical slots (once per read) and
-    // the part from the new slots (per combination, from s_hn)
-    TnDesc db = x.d;
-    int n_new = 0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d)
-        if ((nm >> ((db.slots >> (5 * d)) & 31u)) & 1u) db.J[d] = 0;
-    for (uint32_t b = nm; b; b &= b - 1) ++n_new;
-    if (tid < (1 << n_new)) {
-        // combination tid: the bits of tid deposited into the new slots, the
-        // tid-th subset in increasing order, as the update loop visits them
-        uint32_t c = 0;
-        int used = 0;
-        for (int b = 0; b < 32; ++b)
-            if ((nm >> b) & 1u) c |= ((static_cast<uint32_t>(tid) >> used++) & 1u) << b;
-        int hn = 0;
-        for (int d = 0; d < 6; ++d) {
-            const uint32_t sl = (x.d.slots >> (5 * d)) & 31u;
-            if ((nm >> sl) & 1u) hn += x.d.J[d] * (1 - 2 * static_cast<int>((c >> sl) & 1u));
-        }
-        s_hn[tid] = hn;
-    }
-    __syncthreads();
-    // rounds of kTnReadsInFlight reads (all issued before any update), up to
-    // kTnPairsPerThread reads per thread
     double m = 0.0;
-    for (int r0 = 0; r0 < kTnPairsPerThread; r0 += kTnReadsInFlight) {
-        if (tblk * kTnThreads + r0 * stride >= items) break;   // uniform over the work group
-        uint32_t I[kTnReadsInFlight];
-        T t0[kTnReadsInFlight], t1[kTnReadsInFlight];
-#pragma unroll
-        for (int r = 0; r < kTnReadsInFlight; ++r) {
-            const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
-            I[r] = tn_deposit(static_cast<uint32_t>(p), x);
-            t0[r] = t1[r] = TROP ? T(0) : T(1);
-            if (p < items && t > 0) {
-                t0[r] = tab[I[r]];
-                t1[r] = x.a_active ? tab[I[r] | abit] : t0[r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < kTnReadsInFlight; ++r) {
-            const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
+    if (x.fused) {
+        // steps t0 and t0 + 1 of one read assignment after another: the
+        // assignment's entries (slot a, and slot b of the second step when
+        // canonical) are read, the first step's values kept in s_v (indexed
+        // by their bits at b and the first step's new slots), and only the
+        // second step's entries written
+        const uint32_t bbit = 1u << x.d1.a;
+        const uint32_t nm1 = x.newmask1;
+        const uint32_t X = nm | (x.b_mode == 1 ? bbit : 0u);
+        const uint32_t keep = nm & ~bbit;
+        const int nta = x.b_mode == 1 ? 2 : 1;
+        for (int k = 0; k < kTnPairsPerThread; ++k) {
+            const int64_t p = tblk * kTnThreads + tid + k * stride;
             if (p >= items) break;
-            const int hb = tn_field_raw(db, I[r]);
-            uint32_t c = 0;
-            int kc = 0;
-            do {
-                const uint32_t O = I[r] | c;
-                const int hh = min(max(hb + s_hn[kc++], -kTnHMax), kTnHMax);
-                T v;
-                if (TROP) {
-                    v = min(t0[r] + hh, t1[r] - hh);
-                } else {
-                    v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
-                    m = fmax(m, static_cast<double>(v));
+            uint32_t q = static_cast<uint32_t>(p);
+            if (x.b_mode == 1) q = tn_pair_index(q, x.b_rank);   // b's place among the canonical bits: 0
+            const uint32_t I = tn_deposit(q, x);
+            T r0[2], r1[2];
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                r0[ta] = r1[ta] = TROP ? T(0) : T(1);
+                if (ta < nta && t > 0) {
+                    const uint32_t Ib = I | (ta ? bbit : 0u);
+                    r0[ta] = tab[Ib];
+                    r1[ta] = x.a_active ? tab[Ib | abit] : r0[ta];
                 }
-                tab[O] = v;
-                c = (c - nm) & nm;
-            } while (c != 0);
+            }
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                if (ta >= nta) break;
+                uint32_t c = 0;
+                do {
+                    const uint32_t idx = I | (ta ? bbit : 0u) | c;
+                    const int hh = tn_field(x.d, idx);
+                    T v;
+                    if (TROP)
+                        v = min(r0[ta] + hh, r1[ta] - hh);
+                    else
+                        v = tn_pair_sum(r0[ta], w[kTnHMax + hh], r1[ta], w[kTnHMax - hh], scale);
+                    s_v[tn_extract(idx, X)][tid] = v;
+                    c = (c - nm) & nm;
+                } while (c != 0);
+            }
+            uint32_t c0 = 0;
+            do {
+                const uint32_t B = I | c0;
+                const T u0 = s_v[tn_extract(B, X)][tid];
+                const T u1 = x.b_mode ? s_v[tn_extract(B | bbit, X)][tid] : u0;
+                uint32_t c1 = 0;
+                do {
+                    const uint32_t O = B | c1;
+                    const int hh = tn_field(x.d1, O);
+                    T v;
+                    if (TROP) {
+                        v = min(u0 + hh, u1 - hh);
+                    } else {
+                        v = tn_pair_sum(u0, w[kTnHMax + hh], u1, w[kTnHMax - hh], 1.0);
+                        m = fmax(m, static_cast<double>(v));
+                    }
+                    tab[O] = v;
+                    c1 = (c1 - nm1) & nm1;
+                } while (c1 != 0);
+                c0 = (c0 - keep) & keep;
+            } while (c0 != 0);
+        }
+    } else {
+        // the field splits into the part from canonical slots (once per read) and
+        // the part from the new slots (per combination, from s_hn)
+        TnDesc db = x.d;
+        int n_new = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d)
+            if ((nm >> ((db.slots >> (5 * d)) & 31u)) & 1u) db.J[d] = 0;
+        for (uint32_t b = nm; b; b &= b - 1) ++n_new;
+        if (tid < (1 << n_new)) {
+            // combination tid: the bits of tid deposited into the new slots, the
+            // tid-th subset in increasing order, as the update loop visits them
+            uint32_t c = 0;
+            int used = 0;
+            for (int b = 0; b < 32; ++b)
+                if ((nm >> b) & 1u) c |= ((static_cast<uint32_t>(tid) >> used++) & 1u) << b;
+            int hn = 0;
+            for (int d = 0; d < 6; ++d) {
+                const uint32_t sl = (x.d.slots >> (5 * d)) & 31u;
+                if ((nm >> sl) & 1u) hn += x.d.J[d] * (1 - 2 * static_cast<int>((c >> sl) & 1u));
+            }
+            s_hn[tid] = hn;
+        }
+        __syncthreads();
+        // rounds of kTnReadsInFlight reads (all issued before any update), up to
+        // kTnPairsPerThread reads per thread
+        for (int r0 = 0; r0 < kTnPairsPerThread; r0 += kTnReadsInFlight) {
+            if (tblk * kTnThreads + r0 * stride >= items) break;   // uniform over the work group
+            uint32_t I[kTnReadsInFlight];
+            T t0[kTnReadsInFlight], t1[kTnReadsInFlight];
+#pragma unroll
+            for (int r = 0; r < kTnReadsInFlight; ++r) {
+                const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
+                I[r] = tn_deposit(static_cast<uint32_t>(p), x);
+                t0[r] = t1[r] = TROP ? T(0) : T(1);
+                if (p < items && t > 0) {
+                    t0[r] = tab[I[r]];
+                    t1[r] = x.a_active ? tab[I[r] | abit] : t0[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kTnReadsInFlight; ++r) {
+                const int64_t p = tblk * kTnThreads + tid + (r0 + r) * stride;
+                if (p >= items) break;
+                const int hb = tn_field_raw(db, I[r]);
+                uint32_t c = 0;
+                int kc = 0;
+                do {
+                    const uint32_t O = I[r] | c;
+                    const int hh = min(max(hb + s_hn[kc++], -kTnHMax), kTnHMax);
+                    T v;
+                    if (TROP) {
+                        v = min(t0[r] + hh, t1[r] - hh);
+                    } else {
+                        v = tn_pair_sum(t0[r], w[kTnHMax + hh], t1[r], w[kTnHMax - hh], scale);
+                        m = fmax(m, static_cast<double>(v));
+                    }
+                    tab[O] = v;
+                    c = (c - nm) & nm;
+                } while (c != 0);
+            }
         }
     }
     if (!TROP) {
@@ -489,7 +612,7 @@ __global__ void k_tn_hbm_final(TnJob jb, TnBatch bt)
         r = static_cast<double>(static_cast<int64_t>(tab[0]) + bt.es[tix]);
     } else {
         int64_t e_sum = 0;
-        for (int t = 0; t + 1 < tb.n_steps; ++t) e_sum += bt.emax[tix * bt.steps + t];
+        for (int t = 0; t + 1 < tb.n_rounds; ++t) e_sum += bt.emax[tix * bt.steps + t];
         r = tn_log_result(static_cast<double>(tab[0]), e_sum, jb.beta, bt.es[tix]);
     }
     jb.res[(static_cast<int64_t>(bt.b0 + bi) * bt.n_items_q + bt.res_k0 + k) * 2 + cv] = r;
@@ -559,10 +682,11 @@ int upload(sg_tn_plan &p)
     };
     const bool ok = put(&p.d_shapes, p.shapes.data(), p.shapes.size() * sizeof(TnShape)) &&
                     put(&p.d_steps, p.steps.empty() ? nullptr : p.steps.data(), p.steps.size() * sizeof(TnStep)) &&
+                    put(&p.d_rounds, p.rounds.empty() ? nullptr : p.rounds.data(), p.rounds.size() * sizeof(TnRound)) &&
                     put(&p.d_items, p.items.data(), p.items.size() * sizeof(TnItem)) &&
                     put(&p.d_entry_pre, p.hbm_entry_pre.data(), p.hbm_entry_pre.size() * sizeof(int64_t));
     if (!ok) {
-        for (void **d : {&p.d_shapes, &p.d_steps, &p.d_items, &p.d_entry_pre})
+        for (void **d : {&p.d_shapes, &p.d_steps, &p.d_rounds, &p.d_items, &p.d_entry_pre})
             if (*d) (void)hipFree(*d), *d = nullptr;
         return fail(SG_ENOMEM, "sg_tn_decimate: uploading the plan");
     }
@@ -612,6 +736,7 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
     jb.score = a.score_out;
     jb.shapes = static_cast<const TnShape *>(p.d_shapes);
     jb.steps = static_cast<const TnStep *>(p.d_steps);
+    jb.rounds = static_cast<const TnRound *>(p.d_rounds);
     jb.items = static_cast<const TnItem *>(p.d_items);
     jb.res = static_cast<double *>(a.workspace);
     jb.L = p.L;
@@ -619,6 +744,9 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
     jb.l = p.l;
     jb.N = static_cast<int64_t>(p.L) * p.L * p.L;
     jb.beta = a.beta;
+    // fused rounds keep two steps' growth before a renormalisation: bounded
+    // for beta <= SG_TN_FUSE_BETA_MAX (the min-plus form never overflows)
+    jb.fuse = (TROP || a.beta <= SG_TN_FUSE_BETA_MAX) ? 1 : 0;
     TnWeights wt{};
     for (int k = -kTnHMax; k <= kTnHMax; ++k) wt.w[k + kTnHMax] = TROP ? 0.0 : std::exp(-a.beta * k);
     const int n_inst = a.n_inst;
@@ -717,18 +845,21 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                 bt.es = reinterpret_cast<int32_t *>(q);
                 q += align256(nt * 4);
                 bt.tables = q;
-                int max_steps = 0;
-                for (int k = R.k0; k < R.k1; ++k)
-                    max_steps = std::max(max_steps, p.shapes[p.items[bt.item_hbm0 + k].shape].n_steps);
+                int max_rounds = 0;
+                for (int k = R.k0; k < R.k1; ++k) {
+                    const TnShape &sh = p.shapes[p.items[bt.item_hbm0 + k].shape];
+                    max_rounds = std::max(max_rounds, jb.fuse ? sh.n_rounds : sh.n_steps);
+                }
                 hipLaunchKernelGGL(k_tn_hbm_prep, dim3(static_cast<uint32_t>((nt * steps + 255) / 256)), dim3(256), 0, bs,
                                    jb, bt);
                 hipLaunchKernelGGL(k_tn_hbm_blocks, dim3(static_cast<uint32_t>((steps + 63) / 64)), dim3(64), 0, bs, jb, bt);
-                for (int t = 0; t < max_steps; ++t) {
-                    // work groups of one (instance, value) at this step: as k_tn_hbm_blocks
+                for (int t = 0; t < max_rounds; ++t) {
+                    // work groups of one (instance, value) in this round: as k_tn_hbm_blocks
                     int64_t blocks_t = 0;
                     for (int k = R.k0; k < R.k1; ++k) {
                         const TnShape &sh = p.shapes[p.items[bt.item_hbm0 + k].shape];
-                        if (t < sh.n_steps) blocks_t += tn_table_blocks(p.steps[sh.step0 + t].n_base);
+                        if (t < (jb.fuse ? sh.n_rounds : sh.n_steps))
+                            blocks_t += tn_table_blocks(tn_round(p.rounds.data(), p.steps.data(), sh, t, jb.fuse).read_bits);
                     }
                     if (blocks_t == 0) continue;
                     hipLaunchKernelGGL(k_tn_hbm_step<TROP>, dim3(static_cast<uint32_t>(int64_t{R.nb} * 2 * blocks_t)),
@@ -801,7 +932,7 @@ int sg_tn_plan_destroy(sg_tn_plan *p)
     clear_error();
     for (void *x : {p->side, p->side2})
         if (x) (void)hipStreamSynchronize(static_cast<hipStream_t>(x));
-    for (void *d : {p->d_shapes, p->d_steps, p->d_items, p->d_entry_pre})
+    for (void *d : {p->d_shapes, p->d_steps, p->d_rounds, p->d_items, p->d_entry_pre})
         if (d) (void)hipFree(d);
     for (void *x : {p->side, p->side2})
         if (x) (void)hipStreamDestroy(static_cast<hipStream_t>(x));
@@ -816,8 +947,8 @@ int sg_tn_decimate(sg_tn_plan *p, const sg_tn_args *a, void *stream)
     if (!p || !a) return fail(SG_EINVAL, "sg_tn_decimate: NULL plan or args");
     if (!a->J || !a->spins_out || !a->workspace) return fail(SG_EINVAL, "sg_tn_decimate: NULL J, spins_out or workspace");
     if (a->n_inst < 1 || a->n_inst > (1 << 16)) return fail(SG_EINVAL, "sg_tn_decimate: n_inst = %d", a->n_inst);
-    if (!a->tropical && !(a->beta > 0.0 && a->beta <= 20.0))
-        return fail(SG_EINVAL, "sg_tn_decimate: beta = %g outside (0, 20]", a->beta);
+    if (!a->tropical && !(a->beta > 0.0 && a->beta <= 14.0))
+        return fail(SG_EINVAL, "sg_tn_decimate: beta = %g outside (0, 14]", a->beta);
     const int64_t need = sg_tn_workspace_bytes(p, a->n_inst, 0);
     if (a->workspace_bytes < need)
         return fail(SG_EINVAL, "sg_tn_decimate: workspace %lld bytes < %lld", static_cast<long long>(a->workspace_bytes),

@@ -50,14 +50,37 @@ struct TnStep {
 };
 static_assert(sizeof(TnStep) == 32, "TnStep layout");
 
+// A round is one step, or two consecutive steps t, t + 1 ("fused") that
+// the workspace tier runs in one pass: every assignment of the canonical
+// slots of step t other than the slot b of step t + 1 reads its entries
+// (a and b = 0, 1 where active), applies step t to them in registers, then
+// step t + 1, and writes only step t + 1's entries.  Sum-product tables are
+// renormalised after each round (so both tiers renormalise there).  Steps
+// are paired greedily from the first; a pair is fused when step t + 1 is not
+// the last step and step t leaves at most kTnFuseMax values per read
+// assignment (2^|new slots of t|, twice that when b is canonical at t).
+constexpr int kTnFuseMax = 8;
+
+struct TnRound {
+    int16_t step;      // first step, within its shape
+    uint8_t fused;     // 1: also runs step + 1
+    uint8_t read_bits; // canonical read bits of the round (bits of p per read assignment)
+    uint8_t b_mode;    // slot b of step + 1: 0 new at step + 1, 1 canonical at step, 2 new at step
+    uint8_t b_rank;    //   its rank among step's canonical bits (mode 1)
+    uint8_t pad[2];
+};
+static_assert(sizeof(TnRound) == 8, "TnRound layout");
+
 struct TnShape {
     int32_t W;         // table bits (2^W entries)
     int32_t n_steps;   // eliminations
     int32_t step0;     // first step in the step array
     int8_t ccode[6];   // the centre's neighbours: kTnConst (fixed) or kTnNone
     int16_t max_base;  // most canonical read bits of a step (workspace tier)
+    int32_t round0;    // first round in the round array
+    int32_t n_rounds;
 };
-static_assert(sizeof(TnShape) == 20, "TnShape layout");
+static_assert(sizeof(TnShape) == 28, "TnShape layout");
 
 struct TnItem {
     int32_t site;      // global index of the centre
@@ -80,6 +103,7 @@ struct sg_tn_plan {
     int32_t L = 0, h = 0, l = 0, order = 0, lds_bits = 0;
     std::vector<sg::TnShape> shapes;
     std::vector<sg::TnStep> steps;
+    std::vector<sg::TnRound> rounds;
     std::vector<sg::TnItem> items;
     std::vector<sg::TnPhase> phases;
     // workspace items in phase order: table-entry prefix of one instance
@@ -90,7 +114,7 @@ struct sg_tn_plan {
     // device copies (first decimation)
     std::mutex mu;
     int device = -1;
-    void *d_shapes = nullptr, *d_steps = nullptr, *d_items = nullptr;
+    void *d_shapes = nullptr, *d_steps = nullptr, *d_rounds = nullptr, *d_items = nullptr;
     void *d_entry_pre = nullptr;
     // the LDS tier runs beside the workspace tier on a stream of the plan
     // (default priority), forked from and joined to the caller's stream

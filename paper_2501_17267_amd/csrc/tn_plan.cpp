@@ -147,6 +147,37 @@ std::vector<int> best_order(const Frag &f, const std::vector<int> &V)
 }
 
 // the elimination program of one shape
+// the shape's rounds (see TnRound), pairing its steps greedily from the first
+void plan_rounds(TnShape &sh, const std::vector<TnStep> &steps, std::vector<TnRound> &rounds)
+{
+    sh.round0 = static_cast<int32_t>(rounds.size());
+    for (int t = 0; t < sh.n_steps;) {
+        const TnStep &s0 = steps[sh.step0 + t];
+        TnRound R{};
+        R.step = static_cast<int16_t>(t);
+        R.read_bits = s0.n_base;
+        if (t + 2 < sh.n_steps) {
+            const TnStep &s1 = steps[sh.step0 + t + 1];
+            uint32_t base = 0;
+            for (int r = 0; r < s0.n_runs; ++r) base |= ((1u << s0.run_len[r]) - 1u) << s0.run_start[r];
+            const uint32_t bbit = 1u << s1.a;
+            const int mode = (base & bbit) ? 1 : (s0.newmask & bbit) ? 2 : 0;
+            const int kept = (1 << __builtin_popcount(s0.newmask)) * (mode == 1 ? 2 : 1);
+            if (kept <= kTnFuseMax && s1.a_active == (mode != 0) && s1.a != s0.a) {
+                R.fused = 1;
+                R.b_mode = static_cast<uint8_t>(mode);
+                if (mode == 1) {
+                    R.b_rank = static_cast<uint8_t>(__builtin_popcount(base & (bbit - 1u)));
+                    R.read_bits = static_cast<uint8_t>(s0.n_base - 1);
+                }
+            }
+        }
+        rounds.push_back(R);
+        t += 1 + R.fused;
+    }
+    sh.n_rounds = static_cast<int32_t>(rounds.size()) - sh.round0;
+}
+
 TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
 {
     std::vector<int> V;
@@ -285,7 +316,8 @@ int sg_tn_plan_create(int32_t L, int32_t halo, int32_t order, int32_t lds_max_bi
             int id;
             if (it == ids.end()) {
                 Frag f{l, n3, n3 / 2, m};
-                const TnShape sh = plan_shape(f, p->steps);
+                TnShape sh = plan_shape(f, p->steps);
+                plan_rounds(sh, p->steps, p->rounds);
                 if (sh.W > SG_TN_MAX_BITS) {
                     delete p;
                     return fail(SG_EUNSUPPORTED, "sg_tn_plan_create: a fragment needs a table of 2^%d entries", sh.W);
@@ -404,6 +436,27 @@ int sg_tn_plan_program(const sg_tn_plan *p, int32_t *n_shapes, int32_t *shapes, 
         for (size_t i = 0; i < p->items.size(); ++i) {
             items[2 * i + 0] = p->items[i].site;
             items[2 * i + 1] = p->items[i].shape;
+        }
+    return SG_OK;
+}
+
+int sg_tn_plan_rounds(const sg_tn_plan *p, int32_t *n_rounds, int32_t *shape_rounds, int32_t *rounds)
+{
+    if (!p || !n_rounds) return fail(SG_EINVAL, "sg_tn_plan_rounds: NULL pointer");
+    clear_error();
+    *n_rounds = static_cast<int32_t>(p->rounds.size());
+    if (shape_rounds)
+        for (size_t i = 0; i < p->shapes.size(); ++i) {
+            shape_rounds[2 * i + 0] = p->shapes[i].round0;
+            shape_rounds[2 * i + 1] = p->shapes[i].n_rounds;
+        }
+    if (rounds)
+        for (size_t i = 0; i < p->rounds.size(); ++i) {
+            const TnRound &R = p->rounds[i];
+            rounds[4 * i + 0] = R.step;   // within its shape
+            rounds[4 * i + 1] = R.fused;
+            rounds[4 * i + 2] = R.read_bits;
+            rounds[4 * i + 3] = R.b_mode | (R.b_rank << 8);
         }
     return SG_OK;
 }

@@ -22,32 +22,51 @@ from . import TnPlan, make_instance, tn_decimate
 from . import workloads as wl
 
 
-def workspace_step_bytes(L, h, n_inst, elem, order=1):
+def workspace_step_bytes(L, h, n_inst, elem, order=1, fused=True):
     """Algorithmic bytes the workspace tier's step kernel moves in one
     decimation of n_inst instances: for every workspace-tier table (both
-    centre values) and every step, elem bytes per canonical read (none at
-    the first step, two where the eliminated slot is active) and per written
-    entry.  Host only: from the plan's exported programs."""
+    centre values) and every round, elem bytes per canonical read (none at
+    the first step; two where the eliminated slot is active, twice that
+    again where a fused round's second slot is canonical) and per entry the
+    round writes (a fused round writes only its second step's entries).
+    fused=False counts every step as its own round (beta above
+    SG_TN_FUSE_BETA_MAX).  Host only: from the plan's exported programs."""
     plan = TnPlan(L, h, order)
     shapes, steps, items = plan.program()
+    shape_rounds, rounds = plan.rounds()
     lds_bits = plan.info()["lds_max_bits"]
     plan.close()
     per_shape = {}
     total = 0
     for _, s in items:
-        W, ns, s0 = int(shapes[s][0]), int(shapes[s][1]), int(shapes[s][2])
-        if W <= lds_bits:
+        if int(shapes[s][0]) <= lds_bits:
             continue
         if s not in per_shape:
-            b = 0
-            for t in range(ns):
-                row = steps[s0 + t]
-                a_act, n_base, nm = int(row[8]), int(row[10]), int(row[11]) & 0xFFFFFFFF
-                reads = 0 if t == 0 else (2 if a_act else 1)
-                b += (1 << n_base) * (reads + (1 << bin(nm).count("1"))) * elem
-            per_shape[s] = b
+            per_shape[s] = shape_step_entries(shapes, steps, shape_rounds, rounds, s, fused) * elem
         total += 2 * per_shape[s]
     return total * n_inst
+
+
+def shape_step_entries(shapes, steps, shape_rounds, rounds, s, fused=True):
+    """Entries one table of shape s moves through the workspace tier's
+    rounds: canonical reads plus written entries (see workspace_step_bytes)."""
+    pc = lambda v: bin(v).count("1")
+    ns, s0 = int(shapes[s][1]), int(shapes[s][2])
+    rows = ([(t, 0, 0, 0) for t in range(ns)] if not fused else
+            [tuple(int(v) for v in rounds[r]) for r in range(shape_rounds[s][0], sum(shape_rounds[s]))])
+    n = 0
+    for t, fz, read_bits, bcode in rows:
+        row = steps[s0 + t]
+        a_act, n_base, nm = int(row[8]), int(row[10]), int(row[11]) & 0xFFFFFFFF
+        reads = 0 if t == 0 else (2 if a_act else 1)
+        if not fz:
+            n += (1 << n_base) * (reads + (1 << pc(nm)))
+        else:
+            nxt = steps[s0 + t + 1]
+            bbit, nm1 = 1 << int(nxt[1]), int(nxt[11]) & 0xFFFFFFFF
+            reads *= 2 if (bcode & 0xFF) == 1 else 1
+            n += (1 << read_bits) * (reads + (1 << (pc(nm & ~bbit) + pc(nm1))))
+    return n
 
 
 def study_step_bytes(sizes=(8, 12, 16, 20, 24, 32), n_inst=20, beta_L=12, n_betas=6, n_classes=5):

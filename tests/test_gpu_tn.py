@@ -175,6 +175,31 @@ def test_batch_halves_equal_single_instance_calls(tropical):
         assert en[b] == en1[0]
 
 
+def test_unfused_rounds_above_the_fuse_bound():
+    # beta above SG_TN_FUSE_BETA_MAX: every step is its own round in both
+    # tiers; l = 3 against the oracle with the workspace tier forced, l = 5
+    # tiers bit-identical
+    beta = 12.0
+    L, h = 6, 1
+    log(f"tn l=3 L={L} beta={beta} unfused")
+    plan = sg.TnPlan(L, h, 1, 4)
+    assert plan.info()["n_hbm_sites"] > 0
+    Js, egs = _instances(L, 2, 1212)
+    ws = torch.empty((plan.workspace_bytes(2, full=False) + 7) // 8, dtype=torch.float64, device="cuda")
+    sp, en, sc = _run(plan, Js, beta, False, ws)
+    for b in range(2):
+        ref, rsc = tn.tn_decimate(L, Js[b], h, 1, beta, False)
+        np.testing.assert_array_equal(sp[b], ref, err_msg=f"instance {b}")
+        assert all(_close(float(x), float(y)) for x, y in zip(sc[b], rsc))
+    L, h = 10, 2
+    log(f"tn l=5 L={L} beta={beta}: LDS tier vs workspace tier, unfused")
+    Js, _ = _instances(L, 1, 1213)
+    sp13, en13, sc13 = _run(sg.TnPlan(L, h, 1), Js, beta, False)
+    sp8, en8, sc8 = _run(sg.TnPlan(L, h, 1, 8), Js, beta, False)
+    np.testing.assert_array_equal(sp13, sp8)
+    np.testing.assert_array_equal(sc13, sc8)
+
+
 def test_argument_errors():
     plan = sg.TnPlan(6, 1, 1)
     J = torch.zeros((1, 6, 216), dtype=torch.int8, device="cuda")
@@ -182,6 +207,8 @@ def test_argument_errors():
         sg.tn_decimate(plan, J, beta=0.0)
     with pytest.raises(sg.SgError):
         sg.tn_decimate(plan, J, beta=25.0)
+    with pytest.raises(sg.SgError):
+        sg.tn_decimate(plan, J, beta=15.0)   # above the bound where no table overflows
     small = torch.empty(1, dtype=torch.float64, device="cuda")
     with pytest.raises(sg.SgError):
         sg.tn_decimate(plan, J, beta=2.0, workspace=small)

@@ -130,9 +130,142 @@ def _execute_canonical(L, h, J, dec, site, shape, steps, beta, tropical, sc):
     return int(T[0]) + es if tropical else log + math.log(T[0]) - beta * es
 
 
+def _terms(L, h, J, dec, site, row, sc):
+    """Field terms of one step: the constant part and (J, slot) per active neighbour."""
+    l = 2 * h + 1
+    lv, codes = int(row[0]), [int(v) for v in row[2:8]]
+    g = _wrap(L, site, lv % l - h, (lv // l) % l - h, lv // (l * l) - h)
+    hc, act = 0, []
+    for d, code in enumerate(codes):
+        if code == -3:
+            continue
+        Jd = int(J[d, g])
+        if code >= 0:
+            act.append((Jd, code))
+        elif code == -1:
+            hc += Jd * int(dec[_wrap(L, g, *_DIRS[d])])
+        else:
+            hc += Jd * sc
+    return hc, act
+
+
+def _subsets(mask):
+    c = 0
+    while True:
+        yield c
+        c = (c - mask) & mask
+        if c == 0:
+            return
+
+
+def _runs(row):
+    n_runs = int(row[9])
+    starts = [(int(row[12 + r // 4]) >> (8 * (r % 4))) & 0xFF for r in range(n_runs)]
+    lens = [(int(row[14 + r // 4]) >> (8 * (r % 4))) & 0xFF for r in range(n_runs)]
+    return starts, lens
+
+
+def _deposit(p, starts, lens):
+    I, used = 0, 0
+    for st, ln in zip(starts, lens):
+        I |= ((p >> used) & ((1 << ln) - 1)) << st
+        used += ln
+    return I
+
+
+def _execute_rounds(L, h, J, dec, site, shape, steps, shape_rounds, rounds, sidx, beta, tropical, sc):
+    """The table by the workspace tier's rule round by round, a fused round
+    (steps t, t + 1) the way the step kernel runs it: per read assignment
+    (canonical slots of t other than slot b of t + 1) the entries at a, b =
+    0, 1 are read, step t's values kept, and only step t + 1's entries
+    written; renormalised after each round.  Also checks that within a
+    round no entry one assignment reads is written by another."""
+    W, ns, s0, cmask = (int(v) for v in shape)
+    r0, nr = (int(v) for v in shape_rounds[sidx])
+    T = np.full(1 << W, -(1 << 40), np.int64) if tropical else np.full(1 << W, np.nan)
+    T[0] = 0 if tropical else 1.0
+    log = 0.0
+    pair = ((lambda t0, t1, hh: min(t0 + hh, t1 - hh)) if tropical else
+            (lambda t0, t1, hh: t0 * math.exp(-beta * hh) + t1 * math.exp(beta * hh)))
+    field = lambda terms, idx: terms[0] + sum(Jd * (1 - 2 * ((idx >> b) & 1)) for Jd, b in terms[1])
+    covered = 0
+    for r in range(nr):
+        t, fused, read_bits, bcode = (int(v) for v in rounds[r0 + r])
+        assert t == covered, "rounds cover the steps in order"
+        row = steps[s0 + t]
+        a, a_active, n_base, nm = int(row[1]), int(row[8]), int(row[10]), int(row[11]) & 0xFFFFFFFF
+        starts, lens = _runs(row)
+        base = _deposit((1 << n_base) - 1, starts, lens)
+        term0 = _terms(L, h, J, dec, site, row, sc)
+        outs, reader, writer = {}, {}, {}
+        if not fused:
+            assert read_bits == n_base
+            for p in range(1 << n_base):
+                I = _deposit(p, starts, lens)
+                t0 = t1 = 0 if tropical else 1.0
+                if t > 0:
+                    t0 = T[I]
+                    t1 = T[I | (1 << a)] if a_active else t0
+                for c in _subsets(nm):
+                    outs[I | c] = pair(t0, t1, field(term0, I | c))
+            covered += 1
+        else:
+            row1 = steps[s0 + t + 1]
+            b, nm1 = int(row1[1]), int(row1[11]) & 0xFFFFFFFF
+            mode, rank = bcode & 0xFF, bcode >> 8
+            assert t + 2 < ns and b != a
+            assert mode == (1 if (base >> b) & 1 else 2 if (nm >> b) & 1 else 0)
+            assert int(row1[8]) == (mode != 0)
+            kept = (1 << bin(nm).count("1")) * (2 if mode == 1 else 1)
+            assert kept <= 8
+            if mode == 1:
+                assert rank == bin(base & ((1 << b) - 1)).count("1") and read_bits == n_base - 1
+            else:
+                assert read_bits == n_base
+            term1 = _terms(L, h, J, dec, site, row1, sc)
+            for p in range(1 << read_bits):
+                q = p if mode != 1 else ((p >> rank) << (rank + 1)) | (p & ((1 << rank) - 1))
+                I = _deposit(q, starts, lens)
+                v0 = {}
+                for ta in ((0, 1) if mode == 1 else (0,)):
+                    Ib = I | (ta << b)
+                    t0 = t1 = 0 if tropical else 1.0
+                    if t > 0:
+                        t0 = T[Ib]
+                        reader.setdefault(Ib, set()).add(p)
+                        if a_active:
+                            t1 = T[Ib | (1 << a)]
+                            reader.setdefault(Ib | (1 << a), set()).add(p)
+                        else:
+                            t1 = t0
+                    for c in _subsets(nm):
+                        v0[Ib | c] = pair(t0, t1, field(term0, Ib | c))
+                assert len(v0) <= 8
+                for c0 in _subsets(nm & ~(1 << b)):
+                    B = I | c0
+                    u0 = v0[B]
+                    u1 = v0[B | (1 << b)] if mode else u0
+                    for c1 in _subsets(nm1):
+                        outs[B | c1] = pair(u0, u1, field(term1, B | c1))
+                        writer[B | c1] = p
+            for loc, ps in reader.items():
+                assert loc not in writer or ps == {writer[loc]}, "an assignment writes what another reads"
+            covered += 2
+        if not tropical:
+            m = max(outs.values())
+            log += math.log(m)
+            outs = {k: v / m for k, v in outs.items()}
+        for O, v in outs.items():
+            T[O] = v
+    assert covered == ns
+    es = sum(int(J[d, site]) * int(dec[_wrap(L, site, *_DIRS[d])]) for d in range(6) if (cmask >> d) & 1) * sc
+    return int(T[0]) + es if tropical else log + math.log(T[0]) - beta * es
+
+
 def _check_plan(L, h, order, n_sample=None, tropical=False, max_bits=None, seed=0):
     plan = sg.TnPlan(L, h, order)
     shapes, steps, items = plan.program()
+    shape_rounds, rounds = plan.rounds()
     info = plan.info()
     assert info["n_shapes"] == len(shapes) and len(items) == L ** 3
     assert sorted(items[:, 0].tolist()) == list(range(L ** 3))
@@ -161,6 +294,14 @@ def _check_plan(L, h, order, n_sample=None, tropical=False, max_bits=None, seed=
         cm = _execute_canonical(L, h, J, dec, site, shapes[shape_of[site]], steps, 2.0, tropical, -1)
         got_c = (cm - cp) if tropical else (cp - cm)
         ref = tn.site_score(L, J, dec, site, h, 2.0, tropical)
+        sidx = shape_of[site]
+        rp = _execute_rounds(L, h, J, dec, site, shapes[sidx], steps, shape_rounds, rounds, sidx, 2.0, tropical, 1)
+        rm = _execute_rounds(L, h, J, dec, site, shapes[sidx], steps, shape_rounds, rounds, sidx, 2.0, tropical, -1)
+        got_r = (rm - rp) if tropical else (rp - rm)
+        if tropical:
+            assert got_r == ref, (site, got_r, ref)
+        else:
+            assert abs(got_r - ref) <= 1e-9 * max(1.0, abs(ref)), (site, got_r, ref)
         if tropical:
             assert got_c == ref, (site, got_c, ref)
         else:
@@ -239,4 +380,39 @@ def test_workspace_step_bytes_accounting():
             a_act, n_base, nm = int(steps[s0 + t][8]), int(steps[s0 + t][10]), int(steps[s0 + t][11]) & 0xFFFFFFFF
             reads = 0 if t == 0 else 1 + a_act
             want += 2 * (reads + 2 ** bin(nm).count("1")) * 2 ** n_base * 8
-    assert one == want
+    assert tn_study.workspace_step_bytes(12, 2, 1, 8, fused=False) == want
+    # fused rounds: the reads and writes of the round rule executed over
+    # index sets (assignments x entries), for the four smallest workspace
+    # shapes; then the total against the per-shape counts
+    shape_rounds, rounds = plan.rounds()
+    hbm_shapes = sorted({int(s) for _, s in items if shapes[s][0] > lb}, key=lambda s: int(shapes[s][0]))
+    assert len(hbm_shapes) > 4
+    for s in hbm_shapes[:4]:
+        W, ns, s0 = (int(v) for v in shapes[s][:3])
+        r0, nr = (int(v) for v in shape_rounds[s])
+        want_f = 0
+        for t, fz, read_bits, bcode in (tuple(int(v) for v in rounds[r0 + r]) for r in range(nr)):
+            row = steps[s0 + t]
+            starts, lens = _runs(row)
+            a, a_act, nm = int(row[1]), int(row[8]), int(row[11]) & 0xFFFFFFFF
+            reads, writes = set(), set()
+            if not fz:
+                for p in range(1 << int(row[10])):
+                    I = _deposit(p, starts, lens)
+                    if t > 0:
+                        reads |= {I, I | (a_act << a)}
+                    writes |= {I | c for c in _subsets(nm)}
+            else:
+                nxt = steps[s0 + t + 1]
+                b, nm1, mode, rank = int(nxt[1]), int(nxt[11]) & 0xFFFFFFFF, bcode & 0xFF, bcode >> 8
+                for p in range(1 << read_bits):
+                    I = _deposit(((p >> rank) << (rank + 1)) | (p & ((1 << rank) - 1)) if mode == 1 else p,
+                                 starts, lens)
+                    for ta in ((0, 1) if mode == 1 else (0,)):
+                        if t > 0:
+                            reads |= {I | (ta << b), I | (ta << b) | (a_act << a)}
+                    writes |= {I | c0 | c1 for c0 in _subsets(nm & ~(1 << b)) for c1 in _subsets(nm1)}
+            want_f += len(reads) + len(writes)
+        assert tn_study.shape_step_entries(shapes, steps, shape_rounds, rounds, s) == want_f
+    per = {int(s): tn_study.shape_step_entries(shapes, steps, shape_rounds, rounds, int(s)) for s in hbm_shapes}
+    assert one == sum(2 * per[int(s)] * 8 for _, s in items if int(s) in per) and one < 0.6 * want
