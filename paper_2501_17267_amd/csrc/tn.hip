@@ -466,22 +466,31 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
         const uint32_t X = nm | (x.b_mode == 1 ? bbit : 0u);
         const uint32_t keep = nm & ~bbit;
         const int nta = x.b_mode == 1 ? 2 : 1;
+        // every assignment's reads issued before any update
+        uint32_t Iv[kTnPairsPerThread];
+        T r0v[kTnPairsPerThread][2], r1v[kTnPairsPerThread][2];
+#pragma unroll
+        for (int k = 0; k < kTnPairsPerThread; ++k) {
+            const int64_t p = tblk * kTnThreads + tid + k * stride;
+            uint32_t q = static_cast<uint32_t>(p);
+            if (x.b_mode == 1) q = tn_pair_index(q, x.b_rank);   // b's place among the canonical bits: 0
+            Iv[k] = tn_deposit(q, x);
+#pragma unroll
+            for (int ta = 0; ta < 2; ++ta) {
+                r0v[k][ta] = r1v[k][ta] = TROP ? T(0) : T(1);
+                if (p < items && ta < nta && t > 0) {
+                    const uint32_t Ib = Iv[k] | (ta ? bbit : 0u);
+                    r0v[k][ta] = tab[Ib];
+                    r1v[k][ta] = x.a_active ? tab[Ib | abit] : r0v[k][ta];
+                }
+            }
+        }
+#pragma unroll
         for (int k = 0; k < kTnPairsPerThread; ++k) {
             const int64_t p = tblk * kTnThreads + tid + k * stride;
             if (p >= items) break;
-            uint32_t q = static_cast<uint32_t>(p);
-            if (x.b_mode == 1) q = tn_pair_index(q, x.b_rank);   // b's place among the canonical bits: 0
-            const uint32_t I = tn_deposit(q, x);
-            T r0[2], r1[2];
-#pragma unroll
-            for (int ta = 0; ta < 2; ++ta) {
-                r0[ta] = r1[ta] = TROP ? T(0) : T(1);
-                if (ta < nta && t > 0) {
-                    const uint32_t Ib = I | (ta ? bbit : 0u);
-                    r0[ta] = tab[Ib];
-                    r1[ta] = x.a_active ? tab[Ib | abit] : r0[ta];
-                }
-            }
+            const uint32_t I = Iv[k];
+            const T *r0 = r0v[k], *r1 = r1v[k];
 #pragma unroll
             for (int ta = 0; ta < 2; ++ta) {
                 if (ta >= nta) break;
