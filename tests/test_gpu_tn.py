@@ -175,13 +175,13 @@ def test_batch_halves_equal_single_instance_calls(tropical):
         assert en[b] == en1[0]
 
 
-def test_unfused_rounds_above_the_fuse_bound():
-    # beta above SG_TN_FUSE_BETA_MAX: every step is its own round in both
-    # tiers; l = 3 against the oracle with the workspace tier forced, l = 5
-    # tiers bit-identical
-    beta = 12.0
+@pytest.mark.parametrize("beta", [8.0, 12.0])
+def test_fused_pairs_and_single_steps_at_higher_beta(beta):
+    # beta 8: fused pairs of steps; beta 12 (above SG_TN_FUSE_BETA_MAX):
+    # every step its own round; in both tiers.  l = 3 against the oracle
+    # with the workspace tier forced, l = 5 tiers bit-identical
     L, h = 6, 1
-    log(f"tn l=3 L={L} beta={beta} unfused")
+    log(f"tn l=3 L={L} beta={beta}")
     plan = sg.TnPlan(L, h, 1, 4)
     assert plan.info()["n_hbm_sites"] > 0
     Js, egs = _instances(L, 2, 1212)
@@ -192,7 +192,7 @@ def test_unfused_rounds_above_the_fuse_bound():
         np.testing.assert_array_equal(sp[b], ref, err_msg=f"instance {b}")
         assert all(_close(float(x), float(y)) for x, y in zip(sc[b], rsc))
     L, h = 10, 2
-    log(f"tn l=5 L={L} beta={beta}: LDS tier vs workspace tier, unfused")
+    log(f"tn l=5 L={L} beta={beta}: LDS tier vs workspace tier")
     Js, _ = _instances(L, 1, 1213)
     sp13, en13, sc13 = _run(sg.TnPlan(L, h, 1), Js, beta, False)
     sp8, en8, sc8 = _run(sg.TnPlan(L, h, 1, 8), Js, beta, False)
