@@ -191,19 +191,48 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
         const int u = f.nbr(f.c, d);
         sh.ccode[d] = (u >= 0 && !bit(f.free, u)) ? kTnConst : kTnNone;
     }
+    // elimination position of every free spin, and the least table width:
+    // the most spins active at once (lowest-free assignment)
+    std::vector<int> pos(f.n3, -1);
+    for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = static_cast<int>(i);
+    int wmin = 0;
+    {
+        std::vector<char> act(f.n3, 0), dn(f.n3, 0);
+        int n_act = 0;
+        for (int v : order) {
+            if (!act[v]) act[v] = 1, ++n_act;
+            for (int d = 0; d < 6; ++d) {
+                const int u = f.nbr(v, d);
+                if (u >= 0 && u != f.c && f.is_free(u) && !dn[u] && !act[u]) act[u] = 1, ++n_act;
+            }
+            wmin = std::max(wmin, n_act);
+            dn[v] = 1;
+            --n_act;
+        }
+    }
     std::vector<int> slot(f.n3, -1);
     std::vector<char> done(f.n3, 0);
     uint64_t used = 0;   // slot occupancy
-    auto take = [&]() {
-        int s = 0;
-        while ((used >> s) & 1u) ++s;
+    // a spin's slot: counted from the bottom, as many slots as active spins
+    // that outlive it (so long-lived spins sit on the low bits), the nearest
+    // free one at or above that, else below; never at or above wmin
+    auto take_for = [&](int w) {
+        int later = 0;
+        for (int u = 0; u < f.n3; ++u)
+            if (slot[u] >= 0 && !done[u] && pos[u] > pos[w]) ++later;
+        later = std::min(later, wmin - 1);
+        int s = -1;
+        for (int q = later; q < wmin && s < 0; ++q)
+            if (!((used >> q) & 1u)) s = q;
+        for (int q = later - 1; q >= 0 && s < 0; --q)
+            if (!((used >> q) & 1u)) s = q;
         used |= uint64_t{1} << s;
         return s;
     };
     int W = 0, max_base = 0;
     uint64_t P = 0;   // canonical (active) slots before the step
     for (int v : order) {
-        if (slot[v] < 0) slot[v] = take();
+        if (slot[v] < 0) slot[v] = take_for(v);
         TnStep st{};
         st.lv = static_cast<int16_t>(v);
         for (int d = 0; d < 6; ++d) {
@@ -216,7 +245,7 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
             else if (!f.is_free(u))
                 code = kTnConst;
             else {
-                if (slot[u] < 0) slot[u] = take();
+                if (slot[u] < 0) slot[u] = take_for(u);
                 code = static_cast<int8_t>(slot[u]);
             }
             st.code[d] = code;
