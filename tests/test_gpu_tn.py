@@ -49,7 +49,7 @@ def _close(a, b):
 
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("tropical", [False, True])
-@pytest.mark.parametrize("lds_bits", [0, 4])
+@pytest.mark.parametrize("lds_bits", [0, 4, 1])
 def test_l3_whole_decimation_equals_the_oracle(order, tropical, lds_bits):
     L, h, n = 6, 1, 3
     log(f"tn l=3 L={L} order={order} tropical={tropical} lds_bits={lds_bits}")
