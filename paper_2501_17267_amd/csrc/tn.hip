@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_hbm_step(TnBatch bt, TnWeight
     const uint32_t nm = x.newmask;
     double m = 0.0;
     if (x.fused) {
-        // steps t0 and t0 + 1 of one read assignment after another: the
+        // the round's two steps, one read assignment after another: the
         // assignment's entries (slot a, and slot b of the second step when
         // canonical) are read, the first step's values kept in s_v (indexed
         // by their bits at b and the first step's new slots), and only the
