@@ -220,11 +220,10 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_lds(TnJob jb, TnWeights wt, i
             e_sum += e_prev;
             scale = ldexp(1.0, -e_prev);
         }
-        for (int t = t0; t < t0 + n_sub; ++t) {
-            const double sc_t = t == t0 ? scale : 1.0;
-            const TnDesc D = desc[t];
+        double m = 0.0;
+        if (n_sub == 1) {
+            const TnDesc D = desc[t0];
             const uint32_t abit = 1u << D.a;
-            double m = 0.0;
             for (int p = tid; p < half; p += kTnThreads) {
                 const uint32_t I0 = tn_pair_index(static_cast<uint32_t>(p), D.a), I1 = I0 | abit;
                 const int hh = tn_field(D, I0);
@@ -232,23 +231,52 @@ __global__ __launch_bounds__(kTnThreads) void k_tn_lds(TnJob jb, TnWeights wt, i
                 if (TROP) {
                     v = min(tab[I0] + hh, tab[I1] - hh);
                 } else {
-                    v = tn_pair_sum(tab[I0], w[kTnHMax + hh], tab[I1], w[kTnHMax - hh], sc_t);
+                    v = tn_pair_sum(tab[I0], w[kTnHMax + hh], tab[I1], w[kTnHMax - hh], scale);
                     m = fmax(m, static_cast<double>(v));
                 }
                 tab[I0] = v;
                 tab[I1] = v;
             }
-            // the exponent after the round's last step is the one kept
-            if (!TROP) {
-                const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
-                if ((tid & 63) == 0) s_emax[(t & 1) * (kTnThreads / 64) + (tid >> 6)] = e;
+        } else {
+            // a fused pair in one pass: each thread takes the four entries at
+            // slots a, b = 0, 1 of an index, applies the first step to both
+            // pairs along a and the second to the pair along b (the same
+            // operations as two passes, without the barrier between them)
+            const TnDesc D0 = desc[t0], D1 = desc[t0 + 1];
+            const uint32_t abit = 1u << D0.a, bbit = 1u << D1.a;
+            const int lo = min(D0.a, D1.a), hi = max(D0.a, D1.a);
+            for (int p = tid; p < (half >> 1); p += kTnThreads) {
+                const uint32_t I = tn_pair_index(tn_pair_index(static_cast<uint32_t>(p), lo), hi);
+                const T e00 = tab[I], e10 = tab[I | abit], e01 = tab[I | bbit], e11 = tab[I | abit | bbit];
+                const int h0 = tn_field(D0, I), h1 = tn_field(D0, I | bbit);
+                const int g0 = tn_field(D1, I), g1 = tn_field(D1, I | abit);
+                T u0, u1;
+                if (TROP) {
+                    const T v0 = min(e00 + h0, e10 - h0), v1 = min(e01 + h1, e11 - h1);
+                    u0 = min(v0 + g0, v1 - g0);
+                    u1 = min(v0 + g1, v1 - g1);
+                } else {
+                    const T v0 = tn_pair_sum(e00, w[kTnHMax + h0], e10, w[kTnHMax - h0], scale);
+                    const T v1 = tn_pair_sum(e01, w[kTnHMax + h1], e11, w[kTnHMax - h1], scale);
+                    u0 = tn_pair_sum(v0, w[kTnHMax + g0], v1, w[kTnHMax - g0], 1.0);
+                    u1 = tn_pair_sum(v0, w[kTnHMax + g1], v1, w[kTnHMax - g1], 1.0);
+                    m = fmax(m, fmax(static_cast<double>(u0), static_cast<double>(u1)));
+                }
+                tab[I] = u0;
+                tab[I | bbit] = u0;
+                tab[I | abit] = u1;
+                tab[I | abit | bbit] = u1;
             }
-            __syncthreads();
-            if (!TROP) {
-                int e = INT_MIN;
-                for (int i = 0; i < kTnThreads / 64; ++i) e = max(e, s_emax[(t & 1) * (kTnThreads / 64) + i]);
-                e_prev = e;
-            }
+        }
+        if (!TROP) {
+            const int e = wave_max_int(m > 0.0 ? ilogb(m) : INT_MIN);
+            if ((tid & 63) == 0) s_emax[(r & 1) * (kTnThreads / 64) + (tid >> 6)] = e;
+        }
+        __syncthreads();
+        if (!TROP) {
+            int e = INT_MIN;
+            for (int i = 0; i < kTnThreads / 64; ++i) e = max(e, s_emax[(r & 1) * (kTnThreads / 64) + i]);
+            e_prev = e;
         }
     }
     if (tid == 0) {
