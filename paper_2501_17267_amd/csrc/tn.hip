@@ -842,8 +842,9 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
                         k0 = k1;
                     }
             }
-            // a batch of several instances runs as two halves, the second on
-            // the plan's second stream with its own part of the workspace
+            // a batch runs as two halves (of its instances, or of one
+            // instance's items), the second on the plan's second stream with
+            // its own part of the workspace
             auto range_bytes = [&](const Range &R) {
                 return batch_bytes(int64_t{2} * R.nb * (R.k1 - R.k0), (epre[R.k1] - epre[R.k0]) * R.nb, steps,
                                    R.k1 - R.k0);
@@ -852,10 +853,21 @@ int run(sg_tn_plan &p, const sg_tn_args &a, hipStream_t st)
             std::vector<Unit> units;
             for (const Range &R : batches) {
                 const Range A{R.b0, R.nb / 2, R.k0, R.k1}, B{R.b0 + R.nb / 2, R.nb - R.nb / 2, R.k0, R.k1};
-                if (R.nb >= 2 && range_bytes(A) + range_bytes(B) <= cap)
+                if (R.nb >= 2 && range_bytes(A) + range_bytes(B) <= cap) {
                     units.push_back({A, B, true});
-                else
-                    units.push_back({R, R, false});
+                    continue;
+                }
+                // one instance: its items in two halves of about equal entries
+                if (R.nb == 1 && R.k1 - R.k0 >= 2) {
+                    int km = R.k0 + 1;
+                    while (km + 1 < R.k1 && 2 * (epre[km] - epre[R.k0]) < epre[R.k1] - epre[R.k0]) ++km;
+                    const Range A1{R.b0, 1, R.k0, km}, B1{R.b0, 1, km, R.k1};
+                    if (range_bytes(A1) + range_bytes(B1) <= cap) {
+                        units.push_back({A1, B1, true});
+                        continue;
+                    }
+                }
+                units.push_back({R, R, false});
             }
             auto launch_batch = [&](const Range &R, char *base, hipStream_t bs) {
                 TnBatch bt{};
