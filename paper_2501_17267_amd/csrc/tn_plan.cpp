@@ -226,6 +226,8 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
             if (!((used >> q) & 1u)) s = q;
         for (int q = later - 1; q >= 0 && s < 0; --q)
             if (!((used >> q) & 1u)) s = q;
+        // never: at most wmin spins are active at once
+        if (s < 0) throw std::length_error("no free slot below the least table width");
         used |= uint64_t{1} << s;
         return s;
     };
@@ -271,7 +273,7 @@ TnShape plan_shape(const Frag &f, std::vector<TnStep> &steps)
             }
             int e = b;
             while (e < 64 && ((base >> e) & 1u)) ++e;
-            if (n_runs == 8) throw std::length_error("more than 8 runs");
+            if (n_runs == 8) throw std::length_error("an elimination step needs more than 8 slot runs");
             st.run_start[n_runs] = static_cast<uint8_t>(b);
             st.run_len[n_runs] = static_cast<uint8_t>(e - b);
             ++n_runs;
@@ -396,9 +398,9 @@ int sg_tn_plan_create(int32_t L, int32_t halo, int32_t order, int32_t lds_max_bi
     } catch (const std::bad_alloc &) {
         delete p;
         return fail(SG_ENOMEM, "sg_tn_plan_create: host allocation");
-    } catch (const std::length_error &) {
+    } catch (const std::length_error &e) {
         delete p;
-        return fail(SG_EUNSUPPORTED, "sg_tn_plan_create: an elimination step needs more than 8 slot runs");
+        return fail(SG_EUNSUPPORTED, "sg_tn_plan_create: %s", e.what());
     }
     *out = p;
     return SG_OK;
