@@ -141,6 +141,9 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
     constexpr int NC = G::NC, C = G::C, SDW = G::SPIN_DW, NI = B::NI;
     uint32_t *sa = s_spin + wa * SDW;
     uint32_t *sb = s_spin + wb * SDW;
+    // the seed's random word follows from the counter alone: drawn first,
+    // its arithmetic beside the loads below
+    const Rand4 uu = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFEu, chain, k0, k1);
     // 1. the disagreeing sites as bits
     uint32_t q[NI], cl[NI];
     int n0[NI], n1[NI];
@@ -179,7 +182,6 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
         if (lane == 0) *size_out = 0;
         return;
     }
-    const Rand4 uu = philox10(static_cast<uint32_t>(k), t, 0xFFFFFFFEu, chain, k0, k1);
     const int r = static_cast<int>((static_cast<uint64_t>(uu.w[0]) * static_cast<uint64_t>(n)) >> 32);
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -231,23 +233,32 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
         __builtin_amdgcn_wave_barrier();
         if (!__any(grown != 0u)) break;
     }
-    // 4. both walkers flip the cluster
+    // 4. both walkers flip the cluster: every dword read first, then every
+    // write (a store to one walker's array could alias a later load from the
+    // other's, so reads and writes in turn would each wait for the last)
     int size = 0;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         const int I = lane + 64 * i;
         if (I >= NC || !cl[i]) continue;
         size += __popc(cl[i]);
+        uint32_t va[2][C], vb[2][C];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int m = 0; m < C; ++m) {
-                const uint32_t bits = (cl[i] >> (c * L + 4 * m)) & B::dword_bits(m);
-                if (!bits) continue;
-                const uint32_t f = B::spread4(bits);
                 const int w = (c * NC + I) * C + m;
-                sa[w] ^= f;
-                sb[w] ^= f;
+                va[c][m] = sa[w];
+                vb[c][m] = sb[w];
+            }
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int m = 0; m < C; ++m) {
+                const uint32_t f = B::spread4((cl[i] >> (c * L + 4 * m)) & B::dword_bits(m));
+                const int w = (c * NC + I) * C + m;
+                sa[w] = va[c][m] ^ f;
+                sb[w] = vb[c][m] ^ f;
             }
     }
     size = wave_sum(size);
