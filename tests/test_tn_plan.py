@@ -416,3 +416,22 @@ def test_workspace_step_bytes_accounting():
         assert tn_study.shape_step_entries(shapes, steps, shape_rounds, rounds, s) == want_f
     per = {int(s): tn_study.shape_step_entries(shapes, steps, shape_rounds, rounds, int(s)) for s in hbm_shapes}
     assert one == sum(2 * per[int(s)] * 8 for _, s in items if int(s) in per) and one < 0.6 * want
+
+
+@pytest.mark.parametrize("L,h,order", [(6, 1, 1), (8, 1, 0), (12, 2, 1), (12, 2, 0), (20, 2, 1)])
+def test_tables_are_as_narrow_as_the_active_spins_allow(L, h, order):
+    # every shape's table has exactly as many index bits as the most spins
+    # active at once in its program (the slot assignment never widens it),
+    # and the slots in use at a step are distinct bits below that width
+    plan = sg.TnPlan(L, h, order)
+    shapes, steps, _ = plan.program()
+    for W, ns, s0, _ in (tuple(int(v) for v in sh) for sh in shapes):
+        active, most = 0, 0
+        for t in range(ns):
+            row = steps[s0 + t]
+            a, nm = int(row[1]), int(row[11]) & 0xFFFFFFFF
+            now = active | nm | (1 << a)   # the slots in use while step t runs
+            assert now >> W == 0
+            most = max(most, bin(now).count("1"))
+            active = now & ~(1 << a)
+        assert most == W and active == 0
