@@ -116,12 +116,20 @@ __device__ __forceinline__ int wave_sum(int v) { return __ockl_wfred_add_i32(v);
 // position of the j-th set bit (j counted from 0) of f
 __device__ __forceinline__ uint32_t nth_bit(uint32_t f, int j)
 {
-    for (int z = 0; z < 32; ++z)
-        if ((f >> z) & 1u) {
-            if (j == 0) return 1u << z;
-            --j;
+    // halving search: the j-th set bit lies in the low half of the window
+    // when the low half holds more than j set bits, else in the high half
+    // (j < popcount(f) at every call)
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const int c = __popc(f & ((1u << w) - 1u));
+        if (j >= c) {
+            j -= c;
+            f >>= w;
+            pos += w;
         }
-    return 0u;
+    }
+    return 1u << pos;
 }
 
 // The cluster move of one slot between walkers wa and wb (two copies at the
