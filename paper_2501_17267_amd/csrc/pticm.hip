@@ -276,8 +276,15 @@ __device__ void icm_move_wave(uint32_t *s_spin, const uint32_t *s_j, const uint3
     // of the pair's energies (on a boundary bond of the cluster the two
     // walkers agree at the outer site and disagree at the inner one, so the
     // two bond terms cancel before and after), which gives wb's
+    // one colour-0 dword per lane and pass (NC * C dwords spread evenly over
+    // the lanes, rather than whole columns, which leave a part-filled pass)
     int ea = 0;
-    for (int u = lane; u < NC; u += 64) ea += Col::column_energy_of(sa, s_j, u);
+    for (int u = lane; u < NC * C; u += 64) {
+        const int col = u / C, m = u - col * C;
+        const uint32_t kbm = Col::field_dword(sa, s_j, 0, col, m, sa[spin_at<L, kColMajor>(0, col, m)]);
+        const int nvalid = (G::TAIL != 0 && m == C - 1) ? G::TAIL : 4;
+        ea += static_cast<int32_t>(kKbBias) * nvalid - static_cast<int32_t>(byte_sum(kbm & Col::valid(m)));
+    }
     ea = wave_sum(ea);
     if (lane == 0) {
         const int32_t pair = s_E[wa] + s_E[wb];
